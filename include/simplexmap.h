@@ -1,0 +1,163 @@
+/*
+ * simplexmap.h -- C ABI of the MI355X (gfx950) block-space thread maps for
+ * discrete orthogonal m-simplex domains.
+ *
+ * Domain (Section 1, Eq. 1):
+ *     Delta_n^m = { x in Z_+^m : 0 <= x_i <= n, x_1 + ... + x_m <= n },
+ * with C(n+m, m) elements, m in {2, 3, 4}.
+ *
+ * Data layout of every buffer: the (n+1)^m bounding box, row-major, x_1
+ * fastest; element x is at index i(x) = sum_k x_k (n+1)^(k-1).  Buffers are
+ * device pointers owned by the caller; the library never allocates, frees
+ * or retains them.  Elements outside the simplex are never written, and
+ * input elements outside it are never used as data (they may hold anything).
+ *
+ * Work decomposition: the box is cut into tiles of rho^m elements.  The
+ * tiles that meet the simplex form the block simplex
+ *     { b in Z_+^m : b_1 + ... + b_m <= floor(n / rho) },
+ * and one workgroup (the paper's "block", Section 4.1, Theorem 1) processes
+ * one tile.  The H launch maps a reduced workgroup grid onto the block
+ * simplex (Section 4.1: Theorem 1 and eq_map2d for m = 2; Section 4.3: the
+ * 3-D theorem, eq_3simplex_map and its hinge for m = 3; Section 6: the
+ * self-similar set with scale r and replication beta, eq_generic-m, for
+ * m = 4; general n by a native power-of-two part plus shell layers, in the
+ * spirit of Section 4.2's trapezoids).  The BB launch
+ * covers the whole box of tiles and discards tiles outside the simplex
+ * (Section 2, the bounding-box map f(x) = x).
+ *
+ * Operations (Section 5.1, Table tab:tests, plus a hit counter and a hash):
+ *   SMAP_OP_MAP   mapping only; reads and writes nothing.      in, out: unused
+ *   SMAP_OP_ACCUM out[i] = in[i] + 1 (uint32, mod 2^32).        in, out: uint32
+ *                 in == out (in place) is allowed.
+ *   SMAP_OP_HITS  out[i] += 1 (atomic, uint32): coverage probe. out: uint32
+ *   SMAP_OP_HASH  out[i] = hash32(x): FNV-1a over the 32-bit words x_1..x_m
+ *                 (basis 0x811C9DC5, prime 0x01000193) then MurmurHash3's
+ *                 fmix32 finaliser.  Project-defined.          out: uint32
+ *   SMAP_OP_CA2   one Life step, B3/S23 over the Moore 8-neighbourhood,
+ *                 m = 2 only.                                   in, out: uint8
+ *   SMAP_OP_CA3   one step of rule B6/S567 over the 26-neighbourhood,
+ *                 m = 3 only.                                   in, out: uint8
+ *   For CA ops the cells in the simplex must hold 0 or 1 (1 = alive);
+ *   neighbours outside the simplex count as dead; in and out must not
+ *   overlap (ping-pong between two buffers across steps).
+ *
+ * Streams and errors: every launch call enqueues on `stream` (a hipStream_t;
+ * NULL = the null stream) and returns without synchronising.  Arguments are
+ * checked before anything is enqueued; on error nothing is launched and a
+ * negative status is returned.  A launch failure reported by the runtime
+ * returns SMAP_EHIP.  Faults inside a kernel surface at the caller's next
+ * synchronisation.  No call aborts or prints.  All calls are thread-safe.
+ */
+#ifndef SIMPLEXMAP_H
+#define SIMPLEXMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SMAP_OK            0
+#define SMAP_EINVAL       (-1) /* bad m, n, op, pointer or buffer overlap       */
+#define SMAP_EUNSUPPORTED (-2) /* valid but unsupported (r, beta) or tile       */
+#define SMAP_ERANGE       (-3) /* sizes overflow the supported index ranges     */
+#define SMAP_EHIP         (-4) /* the HIP runtime reported a launch error       */
+
+/* operations */
+#define SMAP_OP_MAP   0
+#define SMAP_OP_ACCUM 1
+#define SMAP_OP_HITS  2
+#define SMAP_OP_HASH  3
+#define SMAP_OP_CA2   4
+#define SMAP_OP_CA3   5
+
+/* Description of one launch plan (filled by simplex_plan_info). */
+struct simplex_plan_info {
+    int32_t  m;
+    int32_t  use_bb;          /* 1: bounding-box launch, 0: H launch            */
+    int64_t  n;
+    int32_t  r;               /* 1/r, the reciprocal of the scale (H only)       */
+    int32_t  beta;            /* replication factor (H only)                     */
+    int32_t  rho;             /* tile side in elements                           */
+    int32_t  wg_threads;      /* threads per workgroup                           */
+    int32_t  tile_side_k;     /* K = floor(n/rho) + 1, side of the block simplex */
+    int32_t  native_n;        /* N = 2^j: the native part covers sum(b) <= N-2   */
+    int32_t  shell_layers;    /* L = K - (N-1)                                   */
+    int32_t  n_pieces;        /* pieces of the fused H launch (native + shell)   */
+    uint64_t useful_elements; /* C(n+m, m)                                       */
+    uint64_t useful_tiles;    /* tiles meeting the simplex: C(K-1+m, m)          */
+    uint64_t launched_wgs;    /* workgroups in the launch grid                   */
+    uint64_t native_wgs;      /* of which in the native piece (H only)           */
+    uint64_t full_tiles;      /* tiles lying entirely inside the simplex         */
+};
+
+/*
+ * H launch: run `op` over Delta_n^m with the block-space map H.
+ *   m      2, 3 or 4 (m = 1 needs no map, Section 4).
+ *   n      >= 0.
+ *   r      1/r as an integer: 2 is the paper's r = 1/2; 0 selects the default.
+ *   beta   replication factor; 0 selects the default.  Supported (r, beta):
+ *          m = 2: (2, 2); m = 3: (2, 2) with the hinge fold; m = 4: (2, 3)
+ *          with the fold (default) or (2, 4) without it.  Others return
+ *          SMAP_EUNSUPPORTED.
+ *   op     SMAP_OP_*; CA2 needs m = 2 and CA3 needs m = 3.
+ *   buf_in, buf_out   device pointers to (n+1)^m-element boxes (see above);
+ *          unused pointers may be NULL.
+ *   stream hipStream_t to enqueue on.
+ * Returns SMAP_OK or a negative status.
+ */
+int simplex_map_launch(int m, int64_t n, int r, int beta, int op,
+                       const void *buf_in, void *buf_out, void *stream);
+
+/*
+ * BB launch (the baseline): same operation and buffers as simplex_map_launch,
+ * launched over the whole box of tiles; tiles outside the simplex exit at
+ * once and partial tiles filter their elements (Section 2).  The grid is
+ * 2-D (m = 2), 3-D (m = 3), or 3-D with z = b_3 + kbox * b_4 (m = 4), where
+ * kbox = ceil((n+1)/rho); a y or z extent above 65535 returns SMAP_ERANGE.
+ */
+int simplex_bb_launch(int m, int64_t n, int op,
+                      const void *buf_in, void *buf_out, void *stream);
+
+/* *out = C(n+m, m), the number of elements of Delta_n^m (Eq. 1).
+ * SMAP_ERANGE if it does not fit in 64 bits, SMAP_EINVAL for bad m, n, out. */
+int simplex_count(int m, int64_t n, uint64_t *out);
+
+/* Fill *out with the plan that the corresponding launch would use (no GPU
+ * work).  use_bb selects simplex_bb_launch's plan (r, beta ignored). */
+int simplex_plan_info(int m, int64_t n, int r, int beta, int op, int use_bb,
+                      struct simplex_plan_info *out);
+
+/*
+ * Host-side decode of every workgroup of a plan, in launch order (no GPU
+ * work; the same decode functions the kernels run).  For workgroup w,
+ * tiles[5w] = 1 if it maps onto a tile and 0 if it is discarded, and
+ * tiles[5w+1 .. 5w+m] = its tile coordinates b_1..b_m (unused entries 0).
+ * At most `cap` workgroups are written; *written receives the number of
+ * workgroups of the plan.  tiles may be NULL to only query the count.
+ */
+int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
+                       int32_t *tiles, uint64_t cap, uint64_t *written);
+
+/*
+ * Select the tile side rho and workgroup size for (m, op) in later calls of
+ * this process (both launch kinds).  rho = 0 restores the default.  Only
+ * the compiled combinations are accepted (others: SMAP_EUNSUPPORTED):
+ *   MAP/ACCUM/HITS/HASH  m=2: rho 16, 32, 64, 128 (256 threads)
+ *                        m=3: rho 8, 16 (256 threads)
+ *                        m=4: rho 4, 8 (256 threads)
+ *   CA2 (m=2): rho 64 (64 threads), 128 (128), 256 (256)
+ *   CA3 (m=3): rho 32 (256 threads)
+ * wg_threads = 0 picks the listed size; any other value must match it.
+ */
+int simplex_set_tile(int m, int op, int rho, int wg_threads);
+
+/* Static, human-readable text for a status code. */
+const char *simplex_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIMPLEXMAP_H */

@@ -58,6 +58,9 @@ def _load():
     lib.oracle_cell.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                 ctypes.c_void_p, i64p]
     lib.oracle_cell.restype = ctypes.c_int64
+    lib.oracle_row.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                               i64p, ctypes.c_void_p]
+    lib.oracle_row.restype = ctypes.c_int64
     lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_int64]
     lib.oracle_count.restype = ctypes.c_int64
     u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -124,6 +127,24 @@ def cell(m: int, n: int, op, inp, x) -> int:
     array in which at least the cells the definition reads are filled."""
     xa = (ctypes.c_int64 * m)(*[int(v) for v in x])
     return int(_load().oracle_cell(m, n, _op(op), _ptr(inp), xa))
+
+
+def row(m: int, n: int, op, inp, xhigh) -> np.ndarray:
+    """Expected outputs of the row with x_2..x_m = ``xhigh`` (x_1 = 0 ..).
+
+    ``inp`` is a full-size box array in which at least the cells the
+    definition reads for this row hold their values (may be None for
+    HITS/HASH/MAP)."""
+    code = _op(op)
+    s = sum(int(v) for v in xhigh)
+    if s > n:
+        raise ValueError("row outside the simplex")
+    buf = np.zeros(n - s + 1, dtype=dtype_of(code))
+    xa = (ctypes.c_int64 * (m - 1))(*[int(v) for v in xhigh])
+    got = _load().oracle_row(m, n, code, _ptr(inp), xa, _ptr(buf))
+    if got != len(buf):
+        raise ValueError("oracle_row rejected arguments")
+    return buf
 
 
 def hash32(x) -> int:

@@ -273,6 +273,31 @@ int64_t oracle_cell(int m, int64_t n, int op, const void *in, const int64_t *x)
     }
 }
 
+/* Expected outputs along one row: x_2..x_m fixed to xhigh[0..m-2], x_1 from
+ * 0 to n - (x_2 + ... + x_m).  row_out receives those n+1-sum values
+ * (uint32 or uint8 by op).  Returns the row length, or -1 if the row lies
+ * outside the simplex or the arguments are bad. */
+int64_t oracle_row(int m, int64_t n, int op, const void *in, const int64_t *xhigh, void *row_out)
+{
+    if (m < 2 || m > 4 || n < 0 || op < OR_MAP || op > OR_CA3 || !row_out) return -1;
+    int64_t x[4] = {0, 0, 0, 0}, s = 0;
+    for (int k = 1; k < m; ++k) {
+        x[k] = xhigh[k - 1];
+        if (x[k] < 0) return -1;
+        s += x[k];
+    }
+    if (s > n) return -1;
+    const int64_t len = n - s + 1;
+    for (x[0] = 0; x[0] < len; ++x[0]) {
+        int64_t v = oracle_cell(m, n, op, in, x);
+        if (op == OR_CA2 || op == OR_CA3)
+            ((uint8_t *)row_out)[x[0]] = (uint8_t)v;
+        else
+            ((uint32_t *)row_out)[x[0]] = (uint32_t)v;
+    }
+    return len;
+}
+
 /* Number of elements the nested loops visit (must be C(n+m, m)). */
 int64_t oracle_count(int m, int64_t n)
 {

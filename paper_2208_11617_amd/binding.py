@@ -1,0 +1,163 @@
+"""ctypes binding of ``libsimplexmap.so`` (the C ABI in include/simplexmap.h).
+
+Argument marshalling only: every step of the work runs in the HIP kernels
+behind the C ABI.  Tensors provide device pointers (``data_ptr()``) and the
+stream (``torch.cuda.current_stream().cuda_stream`` by default).  If the
+library has not been built, loading raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsimplexmap.so")
+
+OK, EINVAL, EUNSUPPORTED, ERANGE, EHIP = 0, -1, -2, -3, -4
+OP_MAP, OP_ACCUM, OP_HITS, OP_HASH, OP_CA2, OP_CA3 = range(6)
+OPS = {"map": OP_MAP, "accum": OP_ACCUM, "hits": OP_HITS, "hash": OP_HASH,
+       "ca2": OP_CA2, "ca3": OP_CA3}
+
+# names declared in include/simplexmap.h
+EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
+           "simplex_plan_info", "simplex_plan_tiles", "simplex_set_tile",
+           "simplex_strerror")
+
+
+class SimplexMapError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} (status {status})")
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int32),
+        ("use_bb", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("r", ctypes.c_int32),
+        ("beta", ctypes.c_int32),
+        ("rho", ctypes.c_int32),
+        ("wg_threads", ctypes.c_int32),
+        ("tile_side_k", ctypes.c_int32),
+        ("native_n", ctypes.c_int32),
+        ("shell_layers", ctypes.c_int32),
+        ("n_pieces", ctypes.c_int32),
+        ("useful_elements", ctypes.c_uint64),
+        ("useful_tiles", ctypes.c_uint64),
+        ("launched_wgs", ctypes.c_uint64),
+        ("native_wgs", ctypes.c_uint64),
+        ("full_tiles", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2208_11617_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
+    ci = ctypes.c_int
+    L.simplex_map_launch.argtypes = [ci, i64, ci, ci, ci, vp, vp, vp]
+    L.simplex_map_launch.restype = ci
+    L.simplex_bb_launch.argtypes = [ci, i64, ci, vp, vp, vp]
+    L.simplex_bb_launch.restype = ci
+    L.simplex_count.argtypes = [ci, i64, ctypes.POINTER(u64)]
+    L.simplex_count.restype = ci
+    L.simplex_plan_info.argtypes = [ci, i64, ci, ci, ci, ci, ctypes.POINTER(PlanInfo)]
+    L.simplex_plan_info.restype = ci
+    L.simplex_plan_tiles.argtypes = [ci, i64, ci, ci, ci, ci, vp, u64, ctypes.POINTER(u64)]
+    L.simplex_plan_tiles.restype = ci
+    L.simplex_set_tile.argtypes = [ci, ci, ci, ci]
+    L.simplex_set_tile.restype = ci
+    L.simplex_strerror.argtypes = [ci]
+    L.simplex_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return lib().simplex_strerror(status).decode()
+
+
+def _op(op) -> int:
+    return OPS[op] if isinstance(op, str) else int(op)
+
+
+def _check(status: int, what: str) -> None:
+    if status != OK:
+        raise SimplexMapError(status, what)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    s = getattr(stream, "cuda_stream", stream)
+    return ctypes.c_void_p(int(s) if s else 0)
+
+
+def map_launch(m, n, op, buf_in=None, buf_out=None, r=0, beta=0, stream=None) -> None:
+    """H launch of ``op`` over Delta_n^m on the given (or current) stream."""
+    _check(lib().simplex_map_launch(m, n, r, beta, _op(op), _ptr(buf_in), _ptr(buf_out),
+                                    _stream(stream)), "simplex_map_launch")
+
+
+def bb_launch(m, n, op, buf_in=None, buf_out=None, stream=None) -> None:
+    """Bounding-box launch of ``op`` over Delta_n^m."""
+    _check(lib().simplex_bb_launch(m, n, _op(op), _ptr(buf_in), _ptr(buf_out), _stream(stream)),
+           "simplex_bb_launch")
+
+
+def map_launch_raw(m, n, r, beta, op, in_ptr, out_ptr, stream_ptr) -> int:
+    """Status-returning form with raw integer pointers (for error-path tests)."""
+    return lib().simplex_map_launch(m, n, r, beta, _op(op), in_ptr, out_ptr, stream_ptr)
+
+
+def bb_launch_raw(m, n, op, in_ptr, out_ptr, stream_ptr) -> int:
+    return lib().simplex_bb_launch(m, n, _op(op), in_ptr, out_ptr, stream_ptr)
+
+
+def count(m, n) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().simplex_count(m, n, ctypes.byref(out)), "simplex_count")
+    return out.value
+
+
+def plan_info(m, n, op, use_bb=False, r=0, beta=0) -> dict:
+    info = PlanInfo()
+    _check(lib().simplex_plan_info(m, n, r, beta, _op(op), 1 if use_bb else 0,
+                                   ctypes.byref(info)), "simplex_plan_info")
+    return info.as_dict()
+
+
+def plan_tiles(m, n, op, use_bb=False, r=0, beta=0):
+    """(valid, tiles) numpy arrays: one row per launched workgroup, in order."""
+    import numpy as np
+    total = ctypes.c_uint64(0)
+    L = lib()
+    _check(L.simplex_plan_tiles(m, n, r, beta, _op(op), 1 if use_bb else 0, None, 0,
+                                ctypes.byref(total)), "simplex_plan_tiles")
+    buf = np.zeros((total.value, 5), dtype=np.int32)
+    _check(L.simplex_plan_tiles(m, n, r, beta, _op(op), 1 if use_bb else 0,
+                                buf.ctypes.data_as(ctypes.c_void_p), total.value,
+                                ctypes.byref(total)), "simplex_plan_tiles")
+    return buf[:, 0].astype(bool), buf[:, 1:1 + m]
+
+
+def set_tile(m, op, rho, wg_threads=0) -> None:
+    _check(lib().simplex_set_tile(m, _op(op), rho, wg_threads), "simplex_set_tile")

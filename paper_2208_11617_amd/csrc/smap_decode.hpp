@@ -1,0 +1,241 @@
+// smap_decode.hpp -- block-space maps: workgroup id -> tile of the block simplex.
+//
+// The box is cut into tiles of rho^m elements; the tiles meeting the simplex
+// form the block simplex T_m(K) = { b in Z_+^m : b_1 + ... + b_m <= K-1 },
+// K = floor(n/rho) + 1.  Each function here turns one workgroup id into the
+// coordinates of one tile (or reports that the workgroup has no tile).  All
+// of them are workgroup-uniform integer code (shifts, clz, adds), so on the
+// GPU they live in scalar registers; the host build of the same code backs
+// simplex_plan_tiles, so the decode the kernels run is also testable without
+// a GPU.
+//
+// Coordinates here are 0-based: t[0] is b_1 (the x_1 tile index), etc.
+//
+// H, native part (N = 2^j).  The self-similar set S_N covers T_m(N-1), i.e.
+// the tiles with sum <= N-2, as a cube of side N/2 plus beta recursive
+// corner copies (Section 4.1, Lemma 1; Section 4.3, Lemma 3; Section 6,
+// eq_generic-m with r = 1/2):
+//   m = 2: Theorem 1 / eq_map2d on the grid Pi_{N/2, N-1}: b = 2^floor(log2(w_y+1)),
+//          q = floor(w_x / b), (X, Y) = (w_x + q b, w_y + 2 q b + 1); the image
+//          is { 0 <= X < Y <= N-1 } and becomes the tile (X, N-1-Y).
+//   m = 3: the packed grid (N/2) x (N/2) x (N/2 + N/4) of Section 4.3: the
+//          first cube takes w_z < N/2; above it the 2-D (b, q) decode of
+//          eq_map2d places the cubes of the smaller levels, the stack slot
+//          being w_z - N/2 < b.  A cube cell whose local coordinates sum to
+//          2b-1 or more lies outside the simplex and is reflected by the
+//          hinge (b-1-l_1, b-1-l_2, 2b-1-l_3) onto the third corner of its
+//          sub-simplex, which it covers exactly (the printed hinge has the
+//          z-term 2b-1-L_z; the reflection that lands in the simplex is the
+//          local z' = 2b-1-l_z, i.e. a shift of 2b-1-2 l_z).
+//   m = 4: levels l = 0..j-1 laid out one after another, level l holding
+//          beta^l cubes of side c = N/2^(l+1); the copy index is read in base
+//          beta, digit k choosing the corner axis at recursion depth k.
+//          beta = 3: the fourth corner is reached by the same hinge
+//          (c-1-l_1, c-1-l_2, c-1-l_3, 2c-1-l_4) -- exact for cells whose local
+//          sum is >= 3c-2; cells with 2c-1 <= sum <= 3c-3 are discarded.
+//          beta = 4: no hinge; every cube cell with sum >= 2c-1 is discarded.
+//          The launched count equals eq_generic-m with r = 1/2:
+//          (N^4 - beta^j) / (16 - beta).
+//
+// H, general K.  With N = 2^j the largest power of two such that N-1 <= K,
+// T_m(K) = T_m(N-1) plus L = K-(N-1) shell layers (sum in [N-1, K-1]).  Every
+// shell tile b is reached from its prefix sums S_d = b_1 + ... + b_d: for the
+// first d with S_{d+1} >= N-1 the tile is (base, layers) with base
+// (b_1..b_d) in T_d(N-1) (d >= 2, decoded by the native d-dim map) or
+// b_1 in [0, K) (d = 1), and layer indices i_k = S_{k+1} - (N-1) in [0, L) for
+// k = d..m-1.  Piece d launches base x L^(m-d) workgroups; the ones whose
+// layer indices decrease, or (d = 1) whose b_2 would be negative, are
+// discarded.  This plays the role of Section 4.2's trapezoids (a native
+// triangle plus rectangular pieces, fused into one launch).
+//
+// BB (Section 2): the tile is the workgroup's grid coordinate, f(x) = x; m = 4
+// is linearised into a 3-D grid (z = b_3 + kbox * b_4).
+#pragma once
+
+#include <stdint.h>
+
+#ifndef SMAP_HD
+#if defined(__HIPCC__)
+#define SMAP_HD __host__ __device__ __forceinline__
+#else
+#define SMAP_HD inline
+#endif
+#endif
+
+namespace smap {
+
+constexpr int kMaxLevels = 16;
+
+// Everything a kernel needs to decode its workgroup id.  Passed by value in
+// the kernel arguments (it ends up in scalar registers / the constant cache).
+struct Plan {
+    int32_t m;
+    int32_t n;
+    int32_t rho;
+    int32_t K;          // side of the block simplex
+    int32_t j;          // native N = 2^j (H only)
+    int32_t L;          // shell layers (H only)
+    int32_t beta;       // replication for the 4-D native map (3 or 4)
+    int32_t kbox;       // tiles per axis of the BB launch
+    int32_t npieces;    // 1 (native only) or m (native + m-1 shell pieces)
+    int32_t nlvl;       // levels of the 4-D native map
+    uint32_t total;     // launched workgroups
+    uint32_t piece_start[5];     // piece p = 0 (native), 1..m-1 (shell d = m-p)
+    uint32_t base_count[4];      // workgroups of the base map of each piece
+    uint32_t lvl_start[kMaxLevels + 1];
+    int64_t stride[4];           // element strides (n+1)^k
+};
+
+SMAP_HD uint32_t ilog2u(uint32_t v)  // floor(log2 v), v > 0: 31 - clz(v)
+{
+    return 31u - (uint32_t)__builtin_clz(v);
+}
+
+// ---- native counts -------------------------------------------------------
+
+SMAP_HD uint64_t h2_count(int j) { return (uint64_t(1) << (j - 1)) * ((uint64_t(1) << j) - 1); }
+
+SMAP_HD uint64_t h3_count(int j)
+{
+    uint64_t c0 = uint64_t(1) << (j - 1);
+    return c0 * c0 * (c0 + (c0 >> 1));
+}
+
+// ---- native decodes ------------------------------------------------------
+
+// Theorem 1 / eq_map2d.  Always lands on a tile of T_2(N-1).
+SMAP_HD void h2_native(int j, uint32_t w, int32_t *t)
+{
+    const uint32_t lh = (uint32_t)j - 1u;
+    const uint32_t wx = w & ((1u << lh) - 1u);
+    const uint32_t wy = w >> lh;
+    const uint32_t lb = ilog2u(wy + 1u);          // b = 2^lb
+    const uint32_t q = wx >> lb;                  // q = floor(w_x / b)
+    const uint32_t X = wx + (q << lb);            // w_x + q b
+    const uint32_t Y = wy + (q << (lb + 1u)) + 1u; // w_y + 2 q b + 1
+    t[0] = (int32_t)X;
+    t[1] = (int32_t)((1u << j) - 1u - Y);
+}
+
+// Packed 3-D grid with the hinge.  Returns false for the unused slots.
+SMAP_HD bool h3_native(int j, uint32_t w, int32_t *t)
+{
+    const uint32_t lc0 = (uint32_t)j - 1u;
+    const uint32_t c0 = 1u << lc0;
+    const uint32_t wx = w & (c0 - 1u);
+    const uint32_t wy = (w >> lc0) & (c0 - 1u);
+    const uint32_t wz = w >> (2u * lc0);
+    int32_t o0, o1, cb, l0, l1, l2;
+    if (wz < c0) {  // the first cube, at the origin
+        o0 = 0; o1 = 0; cb = (int32_t)c0;
+        l0 = (int32_t)wx; l1 = (int32_t)wy; l2 = (int32_t)wz;
+    } else {
+        const uint32_t lb = ilog2u(wy + 1u);
+        if (lb >= lc0) return false;              // last row: no level of side N/2 here
+        const uint32_t bb = 1u << lb;
+        const uint32_t z = wz - c0;
+        if (z >= bb) return false;                // stack slot above a smaller cube
+        const uint32_t q = wx >> lb;
+        cb = (int32_t)bb;
+        l0 = (int32_t)(wx & (bb - 1u));
+        l1 = (int32_t)(bb - 1u - (wy + 1u - bb));
+        l2 = (int32_t)z;
+        o0 = (int32_t)(q << (lb + 1u));
+        o1 = (int32_t)((1u << j) - (bb << 1) - (q << (lb + 1u)));
+    }
+    if (l0 + l1 + l2 >= 2 * cb - 1) {             // hinge onto the third corner
+        t[0] = o0 + cb - 1 - l0;
+        t[1] = o1 + cb - 1 - l1;
+        t[2] = 2 * cb - 1 - l2;
+    } else {
+        t[0] = o0 + l0;
+        t[1] = o1 + l1;
+        t[2] = l2;
+    }
+    return true;
+}
+
+// Level-ordered 4-D map with replication beta (3: hinge, 4: none).
+SMAP_HD bool h4_native(const Plan &P, uint32_t w, int32_t *t)
+{
+    int l = 0;
+    while (l + 1 < P.nlvl && w >= P.lvl_start[l + 1]) ++l;
+    const uint32_t i = w - P.lvl_start[l];
+    const uint32_t lc = (uint32_t)(P.j - 1 - l);
+    const uint32_t c = 1u << lc;
+    const uint32_t cell = i & ((1u << (4u * lc)) - 1u);
+    uint32_t q = i >> (4u * lc);
+    int32_t lam[4], o[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) lam[k] = (int32_t)((cell >> (uint32_t(k) * lc)) & (c - 1u));
+    const uint32_t beta = (uint32_t)P.beta;
+    for (int k = l; k >= 1; --k) {                // corner chosen at depth k
+        const uint32_t d = q % beta;
+        q /= beta;
+        o[d] += (int32_t)((1u << P.j) >> k);
+    }
+    const int32_t ci = (int32_t)c;
+    const int32_t s = lam[0] + lam[1] + lam[2] + lam[3];
+    if (s >= 2 * ci - 1) {
+        if (P.beta == 4 || s < 3 * ci - 2) return false;
+        t[0] = o[0] + ci - 1 - lam[0];
+        t[1] = o[1] + ci - 1 - lam[1];
+        t[2] = o[2] + ci - 1 - lam[2];
+        t[3] = o[3] + 2 * ci - 1 - lam[3];
+    } else {
+        for (int k = 0; k < 4; ++k) t[k] = o[k] + lam[k];
+    }
+    return true;
+}
+
+// ---- H: native + shell pieces ------------------------------------------------
+
+SMAP_HD bool decode_h(const Plan &P, uint32_t w, int32_t *t)
+{
+    const int m = P.m;
+    int p = 0;
+    while (p + 1 < P.npieces && w >= P.piece_start[p + 1]) ++p;
+    const uint32_t loc = w - P.piece_start[p];
+    if (p == 0) {
+        if (m == 2) { h2_native(P.j, loc, t); return true; }
+        if (m == 3) return h3_native(P.j, loc, t);
+        return h4_native(P, loc, t);
+    }
+    const int d = m - p;                          // base dimension of this piece
+    const uint32_t bc = P.base_count[p];
+    const uint32_t base = loc % bc;
+    uint32_t lay = loc / bc;
+    if (d == 1) {
+        t[0] = (int32_t)base;
+    } else if (d == 2) {
+        h2_native(P.j, base, t);
+    } else {
+        if (!h3_native(P.j, base, t)) return false;
+    }
+    const int32_t h = (1 << P.j) - 1;
+    int32_t s = 0;
+    for (int k = 0; k < d; ++k) s += t[k];
+    const uint32_t L = (uint32_t)P.L;
+    for (int k = d; k < m; ++k) {
+        const int32_t ik = (int32_t)(lay % L);
+        lay /= L;
+        t[k] = h + ik - s;
+        if (t[k] < 0) return false;
+        s = h + ik;
+    }
+    return true;
+}
+
+// ---- BB ---------------------------------------------------------------------
+
+SMAP_HD void decode_bb(const Plan &P, uint32_t gx, uint32_t gy, uint32_t gz, int32_t *t)
+{
+    t[0] = (int32_t)gx;
+    t[1] = (int32_t)gy;
+    if (P.m == 3) t[2] = (int32_t)gz;
+    if (P.m == 4) {
+        t[2] = (int32_t)(gz % (uint32_t)P.kbox);
+        t[3] = (int32_t)(gz / (uint32_t)P.kbox);
+    }
+}
+
+}  // namespace smap

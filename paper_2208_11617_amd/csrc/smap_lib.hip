@@ -1,0 +1,373 @@
+// smap_lib.hip -- the C ABI declared in include/simplexmap.h.
+//
+// Validates arguments, looks up (or builds) the launch plan, and enqueues
+// the kernel for (op, m, rho, H|BB) on the caller's stream.  The only state
+// is the per-process tile table (simplex_set_tile) and the plan cache, both
+// behind one mutex.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "../../include/simplexmap.h"
+#include "smap_ca2.hpp"
+#include "smap_ca3.hpp"
+#include "smap_plan.hpp"
+#include "smap_point.hpp"
+
+using namespace smap;
+
+namespace {
+
+struct TileCfg {
+    int rho;
+    int wg;
+};
+
+// op class: 0 = pointwise (MAP/ACCUM/HITS/HASH), 1 = CA2, 2 = CA3
+int op_class(int op) { return op == OP_CA2 ? 1 : (op == OP_CA3 ? 2 : 0); }
+
+TileCfg default_tile(int m, int cls)
+{
+    if (cls == 1) return {256, 256};
+    if (cls == 2) return {32, 256};
+    if (m == 2) return {32, 256};
+    if (m == 3) return {8, 256};
+    return {4, 256};
+}
+
+bool tile_supported(int m, int cls, int rho, int *wg)
+{
+    if (cls == 0) {
+        *wg = 256;
+        if (m == 2) return rho == 16 || rho == 32 || rho == 64 || rho == 128;
+        if (m == 3) return rho == 8 || rho == 16;
+        return rho == 4 || rho == 8;
+    }
+    if (cls == 1) {
+        if (rho == 64) { *wg = 64; return true; }
+        if (rho == 128) { *wg = 128; return true; }
+        if (rho == 256) { *wg = 256; return true; }
+        return false;
+    }
+    *wg = 256;
+    return m == 3 && rho == 32;
+}
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, TileCfg> g_tiles;  // (m, class) -> override
+
+struct CachedPlan {
+    Plan plan;
+    PlanCounts counts;
+    int status;
+};
+std::map<std::tuple<int, int64_t, int, int, int, int>, CachedPlan> g_plans;  // (m,n,beta,rho,bb,cls)
+
+TileCfg tile_for(int m, int cls)
+{
+    auto it = g_tiles.find({m, cls});
+    return it != g_tiles.end() ? it->second : default_tile(m, cls);
+}
+
+int resolve_rb(int m, int r, int beta, int *beta_out)
+{
+    if (r != 0 && r != 2) return kEunsupported;
+    if (beta == 0) beta = (m == 4) ? 3 : 2;
+    if (m == 2 || m == 3) {
+        if (beta != 2) return kEunsupported;
+    } else if (beta != 3 && beta != 4) {
+        return kEunsupported;
+    }
+    *beta_out = beta;
+    return kOk;
+}
+
+bool box_elems(int m, int64_t n, int64_t *out)
+{
+    __int128 e = 1;
+    for (int k = 0; k < m; ++k) {
+        e *= (__int128)(n + 1);
+        if (e > ((__int128)1 << 56)) return false;
+    }
+    *out = (int64_t)e;
+    return true;
+}
+
+// Plan lookup; also checks that in-tile offsets fit the kernels' 32-bit
+// lane offsets.
+int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C, TileCfg *tc)
+{
+    const int cls = op_class(op);
+    std::lock_guard<std::mutex> lk(g_mu);
+    const TileCfg t = tile_for(m, cls);
+    *tc = t;
+    auto key = std::make_tuple(m, n, bb ? 0 : beta, t.rho, bb ? 1 : 0, cls);
+    auto it = g_plans.find(key);
+    if (it == g_plans.end()) {
+        CachedPlan cp{};
+        cp.status = make_plan(m, n, beta, t.rho, bb, &cp.plan, &cp.counts);
+        if (cp.status == kOk) {
+            // largest offset inside one tile, in bytes (uint32 elements)
+            __int128 span = 0;
+            for (int k = 0; k < m; ++k) span += (__int128)(t.rho + 1) * cp.plan.stride[k];
+            if (span * 4 >= ((__int128)1 << 31)) cp.status = kErange;
+        }
+        if (g_plans.size() > 4096) g_plans.clear();
+        it = g_plans.emplace(key, cp).first;
+    }
+    *P = it->second.plan;
+    if (C) *C = it->second.counts;
+    return it->second.status;
+}
+
+int check_op(int m, int64_t n, int op)
+{
+    if (m < 2 || m > 4 || n < 0) return kEinval;
+    if (op < OP_MAP || op > OP_CA3) return kEinval;
+    if (op == OP_CA2 && m != 2) return kEinval;
+    if (op == OP_CA3 && m != 3) return kEinval;
+    return kOk;
+}
+
+int check_buffers(int m, int64_t n, int op, const void *in, const void *out)
+{
+    int64_t elems;
+    if (!box_elems(m, n, &elems)) return kErange;
+    if (op == OP_ACCUM && (!in || !out)) return kEinval;
+    if ((op == OP_HITS || op == OP_HASH) && !out) return kEinval;
+    if (op == OP_CA2 || op == OP_CA3) {
+        if (!in || !out) return kEinval;
+        const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+        const uintptr_t len = (uintptr_t)elems;
+        if (a < b + len && b < a + len) return kEinval;  // overlapping ping-pong buffers
+    }
+    return kOk;
+}
+
+template <int M, int RHO, int OP, bool BB>
+void launch_point(const Plan &P, dim3 grid, const void *in, void *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_point<M, RHO, OP, BB>), grid, dim3(256), 0, s, P,
+                       (const uint32_t *)in, (uint32_t *)out);
+}
+
+template <int M, int OP, bool BB>
+int dispatch_point_rho(int rho, const Plan &P, dim3 grid, const void *in, void *out, hipStream_t s)
+{
+    if constexpr (M == 2) {
+        switch (rho) {
+        case 16: launch_point<M, 16, OP, BB>(P, grid, in, out, s); return kOk;
+        case 32: launch_point<M, 32, OP, BB>(P, grid, in, out, s); return kOk;
+        case 64: launch_point<M, 64, OP, BB>(P, grid, in, out, s); return kOk;
+        case 128: launch_point<M, 128, OP, BB>(P, grid, in, out, s); return kOk;
+        }
+    } else if constexpr (M == 3) {
+        switch (rho) {
+        case 8: launch_point<M, 8, OP, BB>(P, grid, in, out, s); return kOk;
+        case 16: launch_point<M, 16, OP, BB>(P, grid, in, out, s); return kOk;
+        }
+    } else {
+        switch (rho) {
+        case 4: launch_point<M, 4, OP, BB>(P, grid, in, out, s); return kOk;
+        case 8: launch_point<M, 8, OP, BB>(P, grid, in, out, s); return kOk;
+        }
+    }
+    return kEunsupported;
+}
+
+template <int M, bool BB>
+int dispatch_point(int op, int rho, const Plan &P, dim3 grid, const void *in, void *out,
+                   hipStream_t s)
+{
+    switch (op) {
+    case OP_MAP: return dispatch_point_rho<M, OP_MAP, BB>(rho, P, grid, in, out, s);
+    case OP_ACCUM: return dispatch_point_rho<M, OP_ACCUM, BB>(rho, P, grid, in, out, s);
+    case OP_HITS: return dispatch_point_rho<M, OP_HITS, BB>(rho, P, grid, in, out, s);
+    case OP_HASH: return dispatch_point_rho<M, OP_HASH, BB>(rho, P, grid, in, out, s);
+    }
+    return kEinval;
+}
+
+template <bool BB>
+int dispatch(int m, int op, const TileCfg &tc, const Plan &P, const void *in, void *out,
+             hipStream_t s)
+{
+    dim3 grid;
+    if (BB) {
+        const uint32_t kb = (uint32_t)P.kbox;
+        grid = (m == 2) ? dim3(kb, kb, 1) : (m == 3 ? dim3(kb, kb, kb) : dim3(kb, kb, kb * kb));
+    } else {
+        grid = dim3(P.total, 1, 1);
+    }
+    if (op == OP_CA2) {
+        const uint8_t *i8 = (const uint8_t *)in;
+        uint8_t *o8 = (uint8_t *)out;
+        switch (tc.rho) {
+        case 64: hipLaunchKernelGGL((k_ca2<64, 1, BB>), grid, dim3(64), 0, s, P, i8, o8); return kOk;
+        case 128: hipLaunchKernelGGL((k_ca2<128, 2, BB>), grid, dim3(128), 0, s, P, i8, o8); return kOk;
+        case 256: hipLaunchKernelGGL((k_ca2<256, 4, BB>), grid, dim3(256), 0, s, P, i8, o8); return kOk;
+        }
+        return kEunsupported;
+    }
+    if (op == OP_CA3) {
+        if (tc.rho != 32) return kEunsupported;
+        hipLaunchKernelGGL((k_ca3_32<BB>), grid, dim3(256), 0, s, P, (const uint8_t *)in,
+                           (uint8_t *)out);
+        return kOk;
+    }
+    if (m == 2) return dispatch_point<2, BB>(op, tc.rho, P, grid, in, out, s);
+    if (m == 3) return dispatch_point<3, BB>(op, tc.rho, P, grid, in, out, s);
+    return dispatch_point<4, BB>(op, tc.rho, P, grid, in, out, s);
+}
+
+int do_launch(int m, int64_t n, int r, int beta, int op, const void *in, void *out,
+              void *stream, bool bb)
+{
+    int rc = check_op(m, n, op);
+    if (rc != kOk) return rc;
+    int b = 0;
+    if (!bb) {
+        rc = resolve_rb(m, r, beta, &b);
+        if (rc != kOk) return rc;
+    }
+    rc = check_buffers(m, n, op, in, out);
+    if (rc != kOk) return rc;
+    Plan P;
+    TileCfg tc;
+    rc = get_plan(m, n, b, op, bb, &P, nullptr, &tc);
+    if (rc != kOk) return rc;
+    if (P.total == 0) return kOk;
+    hipStream_t s = (hipStream_t)stream;
+    rc = bb ? dispatch<true>(m, op, tc, P, in, out, s) : dispatch<false>(m, op, tc, P, in, out, s);
+    if (rc != kOk) return rc;
+    return hipGetLastError() == hipSuccess ? kOk : kEhip;
+}
+
+}  // namespace
+
+extern "C" {
+
+int simplex_map_launch(int m, int64_t n, int r, int beta, int op, const void *buf_in,
+                       void *buf_out, void *stream)
+{
+    return do_launch(m, n, r, beta, op, buf_in, buf_out, stream, false);
+}
+
+int simplex_bb_launch(int m, int64_t n, int op, const void *buf_in, void *buf_out, void *stream)
+{
+    return do_launch(m, n, 0, 0, op, buf_in, buf_out, stream, true);
+}
+
+int simplex_count(int m, int64_t n, uint64_t *out)
+{
+    if (m < 1 || m > 64 || n < 0 || !out) return kEinval;
+    return binom_u64((uint64_t)n + (uint64_t)m, (uint64_t)m, out) ? kOk : kErange;
+}
+
+int simplex_plan_info(int m, int64_t n, int r, int beta, int op, int use_bb,
+                      struct simplex_plan_info *out)
+{
+    if (!out) return kEinval;
+    int rc = check_op(m, n, op);
+    if (rc != kOk) return rc;
+    int b = 0;
+    if (!use_bb) {
+        rc = resolve_rb(m, r, beta, &b);
+        if (rc != kOk) return rc;
+    }
+    Plan P;
+    PlanCounts C;
+    TileCfg tc;
+    rc = get_plan(m, n, b, op, use_bb != 0, &P, &C, &tc);
+    if (rc != kOk) return rc;
+    struct simplex_plan_info info{};
+    info.m = m;
+    info.use_bb = use_bb ? 1 : 0;
+    info.n = n;
+    info.r = use_bb ? 0 : 2;
+    info.beta = use_bb ? 0 : b;
+    info.rho = tc.rho;
+    info.wg_threads = tc.wg;
+    info.tile_side_k = P.K;
+    info.native_n = use_bb ? 0 : (1 << P.j);
+    info.shell_layers = use_bb ? 0 : P.L;
+    info.n_pieces = use_bb ? 1 : P.npieces;
+    if (!binom_u64((uint64_t)n + m, (uint64_t)m, &info.useful_elements)) return kErange;
+    info.useful_tiles = C.useful_tiles;
+    info.launched_wgs = C.launched;
+    info.native_wgs = C.native;
+    info.full_tiles = C.full_tiles;
+    *out = info;
+    return kOk;
+}
+
+int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb, int32_t *tiles,
+                       uint64_t cap, uint64_t *written)
+{
+    int rc = check_op(m, n, op);
+    if (rc != kOk) return rc;
+    int b = 0;
+    if (!use_bb) {
+        rc = resolve_rb(m, r, beta, &b);
+        if (rc != kOk) return rc;
+    }
+    Plan P;
+    TileCfg tc;
+    rc = get_plan(m, n, b, op, use_bb != 0, &P, nullptr, &tc);
+    if (rc != kOk) return rc;
+    if (written) *written = P.total;
+    if (!tiles) return kOk;
+    const uint64_t cnt = P.total < cap ? P.total : cap;
+    const uint32_t kb = (uint32_t)P.kbox;
+    for (uint64_t w = 0; w < cnt; ++w) {
+        int32_t t[4] = {0, 0, 0, 0};
+        bool ok;
+        if (use_bb) {
+            const uint32_t gx = (uint32_t)(w % kb), gy = (uint32_t)((w / kb) % kb);
+            const uint32_t gz = (uint32_t)(w / ((uint64_t)kb * kb));
+            decode_bb(P, gx, gy, gz, t);
+            int64_t s = 0;
+            for (int k = 0; k < m; ++k) s += (int64_t)t[k] * tc.rho;
+            ok = s <= n;
+        } else {
+            ok = decode_h(P, (uint32_t)w, t);
+        }
+        int32_t *o = tiles + 5 * w;
+        o[0] = ok ? 1 : 0;
+        for (int k = 0; k < 4; ++k) o[1 + k] = ok ? t[k] : 0;
+    }
+    return kOk;
+}
+
+int simplex_set_tile(int m, int op, int rho, int wg_threads)
+{
+    int rc = check_op(m, 0, op);
+    if (rc != kOk) return rc;
+    const int cls = op_class(op);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (rho == 0) {
+        g_tiles.erase({m, cls});
+        return kOk;
+    }
+    int wg = 0;
+    if (!tile_supported(m, cls, rho, &wg)) return kEunsupported;
+    if (wg_threads != 0 && wg_threads != wg) return kEunsupported;
+    g_tiles[{m, cls}] = TileCfg{rho, wg};
+    return kOk;
+}
+
+const char *simplex_strerror(int status)
+{
+    switch (status) {
+    case SMAP_OK: return "success";
+    case SMAP_EINVAL: return "invalid argument (m, n, op, pointer or overlapping buffers)";
+    case SMAP_EUNSUPPORTED: return "unsupported (r, beta) or tile configuration";
+    case SMAP_ERANGE: return "sizes exceed the supported index range";
+    case SMAP_EHIP: return "the HIP runtime reported a launch error";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

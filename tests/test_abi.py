@@ -1,0 +1,114 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments before launching anything (no GPU needed: every call here fails
+validation or is host-only)."""
+import math
+import os
+import re
+
+import pytest
+
+from paper_2208_11617_amd import binding as smap
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "simplexmap.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(simplex_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared() == sorted(smap.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = smap.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for s in (smap.OK, smap.EINVAL, smap.EUNSUPPORTED, smap.ERANGE, smap.EHIP):
+        assert smap.strerror(s)
+    assert smap.strerror(12345) == "unknown status"
+
+
+def test_count():
+    for m in (1, 2, 3, 4, 7):
+        for n in (0, 1, 5, 128, 1024, 16384):
+            want = math.comb(n + m, m)
+            if want < 1 << 64:
+                assert smap.count(m, n) == want
+            else:
+                with pytest.raises(smap.SimplexMapError):
+                    smap.count(m, n)
+    assert smap.count(4, 128) == 12082785
+    with pytest.raises(smap.SimplexMapError) as e:
+        smap.count(30, 1 << 40)
+    assert e.value.status == smap.ERANGE
+    with pytest.raises(smap.SimplexMapError):
+        smap.count(2, -1)
+
+
+FAKE = 0x10000000  # never dereferenced: every call below fails validation
+
+
+@pytest.mark.parametrize("launch", ["h", "bb"])
+def test_argument_errors(launch):
+    def call(m, n, op, i, o):
+        if launch == "h":
+            return smap.map_launch_raw(m, n, 0, 0, op, i, o, None)
+        return smap.bb_launch_raw(m, n, op, i, o, None)
+
+    assert call(1, 10, smap.OP_ACCUM, FAKE, FAKE) == smap.EINVAL     # m = 1: no map needed
+    assert call(5, 10, smap.OP_ACCUM, FAKE, FAKE) == smap.EINVAL
+    assert call(2, -1, smap.OP_ACCUM, FAKE, FAKE) == smap.EINVAL
+    assert call(2, 10, 6, FAKE, FAKE) == smap.EINVAL                  # unknown op
+    assert call(2, 10, -1, FAKE, FAKE) == smap.EINVAL
+    assert call(3, 10, smap.OP_CA2, FAKE, FAKE + 4096) == smap.EINVAL  # CA2 needs m = 2
+    assert call(2, 10, smap.OP_CA3, FAKE, FAKE + 4096) == smap.EINVAL  # CA3 needs m = 3
+    assert call(2, 10, smap.OP_ACCUM, None, FAKE) == smap.EINVAL
+    assert call(2, 10, smap.OP_ACCUM, FAKE, None) == smap.EINVAL
+    assert call(2, 10, smap.OP_HITS, FAKE, None) == smap.EINVAL
+    assert call(2, 10, smap.OP_HASH, None, None) == smap.EINVAL
+    assert call(2, 10, smap.OP_CA2, FAKE, FAKE) == smap.EINVAL         # in place
+    assert call(2, 10, smap.OP_CA2, FAKE, FAKE + 100) == smap.EINVAL   # overlap (box = 121 B)
+    assert call(3, 10, smap.OP_CA3, FAKE + 1000, FAKE) == smap.EINVAL  # overlap (box = 1331 B)
+    assert call(2, 10, smap.OP_CA2, None, FAKE) == smap.EINVAL
+    assert call(4, 1 << 20, smap.OP_HASH, None, FAKE) == smap.ERANGE   # box too large
+    assert call(2, 1 << 31, smap.OP_ACCUM, FAKE, FAKE) == smap.ERANGE
+
+
+def test_unsupported_r_beta():
+    raw = smap.map_launch_raw
+    assert raw(2, 10, 3, 0, smap.OP_HITS, None, FAKE, None) == smap.EUNSUPPORTED  # r = 1/3
+    assert raw(2, 10, 2, 3, smap.OP_HITS, None, FAKE, None) == smap.EUNSUPPORTED  # beta 3 for m = 2
+    assert raw(3, 10, 2, 4, smap.OP_HITS, None, FAKE, None) == smap.EUNSUPPORTED
+    # m = 4 with the paper's (r, beta) = (1/2, 2) cannot cover the simplex
+    assert raw(4, 10, 2, 2, smap.OP_HITS, None, FAKE, None) == smap.EUNSUPPORTED
+    assert raw(4, 10, 2, 5, smap.OP_HITS, None, FAKE, None) == smap.EUNSUPPORTED
+
+
+def test_set_tile_validation():
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_tile(2, "accum", 24)
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_tile(2, "ca2", 256, wg_threads=64)
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_tile(3, "ca3", 16)
+    smap.set_tile(2, "ca2", 64)
+    assert smap.plan_info(2, 1000, "ca2")["rho"] == 64
+    assert smap.plan_info(2, 1000, "ca2")["wg_threads"] == 64
+    smap.set_tile(2, "ca2", 0)
+    assert smap.plan_info(2, 1000, "ca2")["rho"] == 256
+
+
+def test_plan_info_fields():
+    info = smap.plan_info(2, 16384, "ca2")
+    assert info["useful_elements"] == 134242305
+    assert info["tile_side_k"] == 65 and info["native_n"] == 64 and info["shell_layers"] == 2
+    bb = smap.plan_info(2, 16384, "ca2", use_bb=True)
+    assert bb["launched_wgs"] == 65 * 65 and bb["use_bb"] == 1
+    assert smap.plan_info(4, 128, "hash")["beta"] == 3
+    assert smap.plan_info(4, 128, "hash", beta=4)["beta"] == 4

@@ -1,0 +1,293 @@
+"""GPU parity: the HIP kernels, called through the C ABI, against the oracle.
+
+Integer work, so the bar is bit-exact equality everywhere, including the
+sentinel left untouched outside the simplex.  Small and medium sizes compare
+whole boxes; the workload sizes compare sampled rows (recomputed by the
+oracle from inputs it regenerates itself from the shared seeded generator)
+plus properties that hold at any size: H and BB give identical buffers, and
+nothing outside the simplex is written.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import simplex_inputs as si
+from oracle import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+POINT_TILES = {2: [16, 32, 64, 128], 3: [8, 16], 4: [4, 8]}
+CA2_TILES = [64, 128, 256]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def smap():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_11617_amd import binding  # raises if the library is missing
+    binding.lib()
+    return binding
+
+
+def to_dev(a):
+    t = torch.from_numpy(np.ascontiguousarray(a).view(np.int32 if a.dtype == np.uint32 else np.uint8))
+    return t.cuda()
+
+
+def to_host(t, dtype):
+    return t.cpu().numpy().view(dtype)
+
+
+def launch(smap, kind, m, n, op, d_in, d_out, beta=0):
+    if kind == "h":
+        smap.map_launch(m, n, op, d_in, d_out, beta=beta)
+    else:
+        smap.bb_launch(m, n, op, d_in, d_out)
+    torch.cuda.synchronize()
+
+
+def expected(m, n, op, inp):
+    out = si.sentinel_box(m, n, oracle.dtype_of(op))
+    oracle.apply(m, n, op, inp, out)
+    return out
+
+
+def fresh_out(m, n, op):
+    return si.sentinel_box_torch(m, n, oracle.dtype_of(op) == np.uint8)
+
+
+def same(d, want_dev):
+    return torch.equal(d.reshape(-1), want_dev.reshape(-1))
+
+
+def kinds(m):
+    ks = [("h", 0), ("bb", 0)]
+    if m == 4:
+        ks.append(("h", 4))
+    return ks
+
+
+# --------------------------------------------------------------- pointwise
+
+def _sweep(m):
+    if m == 2:
+        return list(range(0, 66)) + [100, 255, 256, 257, 1000]
+    if m == 3:
+        return list(range(0, 41)) + [63, 64, 65, 100]
+    return list(range(0, 25)) + [31, 32, 33]
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_hits_cover_simplex_exactly_once(smap, m):
+    try:
+        for n in _sweep(m):
+            want = to_dev(expected(m, n, "hits", None))
+            for rho in POINT_TILES[m]:
+                smap.set_tile(m, "hits", rho)
+                for kind, beta in kinds(m):
+                    say(f"hits m={m} n={n} rho={rho} {kind} beta={beta}")
+                    d = fresh_out(m, n, "hits")
+                    launch(smap, kind, m, n, "hits", None, d, beta)
+                    assert same(d, want), (m, n, rho, kind, beta)
+    finally:
+        smap.set_tile(m, "hits", 0)
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+@pytest.mark.parametrize("op", ["accum", "hash"])
+def test_pointwise_parity(smap, m, op):
+    try:
+        for n in _sweep(m)[::3] + _sweep(m)[-4:]:
+            inp = si.box(m, n, "u31", 1000 + n) if op == "accum" else None
+            want = to_dev(expected(m, n, op, inp))
+            d_in = to_dev(inp) if inp is not None else None
+            for rho in POINT_TILES[m]:
+                smap.set_tile(m, op, rho)
+                for kind, beta in kinds(m):
+                    say(f"{op} m={m} n={n} rho={rho} {kind} beta={beta}")
+                    d_out = fresh_out(m, n, op)
+                    launch(smap, kind, m, n, op, d_in, d_out, beta)
+                    assert same(d_out, want), (m, n, rho, kind, beta)
+    finally:
+        smap.set_tile(m, op, 0)
+
+
+def test_accum_in_place_and_wrap(smap):
+    m, n = 2, 333
+    inp = si.box(m, n, "u31", 5)
+    inp[0, 0] = 0xFFFFFFFF
+    want = expected(m, n, "accum", inp)
+    want[~si.inside_mask(m, n)] = inp[~si.inside_mask(m, n)]  # in place: outside keeps input
+    for kind in ("h", "bb"):
+        d = to_dev(inp)
+        launch(smap, kind, m, n, "accum", d, d)
+        assert np.array_equal(to_host(d, np.uint32).reshape(want.shape), want)
+
+
+def test_map_writes_nothing(smap):
+    for m, n in ((2, 300), (3, 50), (4, 20)):
+        d = to_dev(si.sentinel_box(m, n, np.uint32))
+        for kind, beta in kinds(m):
+            launch(smap, kind, m, n, "map", None, None, beta)
+        assert np.all(to_host(d, np.uint32) == si.SENTINEL_U32)
+
+
+# --------------------------------------------------------------- automata
+
+CA2_SIZES = list(range(0, 70)) + [127, 128, 129, 255, 256, 257, 300, 511, 512, 513,
+                                  767, 1000, 1023, 1024, 1025, 2047, 2049]
+
+
+def test_ca2_parity(smap):
+    try:
+        for n in CA2_SIZES:
+            inp = si.box(2, n, "bern", 2000 + n, p=0.3)
+            want = to_dev(expected(2, n, "ca2", inp))
+            d_in = to_dev(inp)
+            for rho in CA2_TILES:
+                smap.set_tile(2, "ca2", rho)
+                for kind in ("h", "bb"):
+                    say(f"ca2 n={n} rho={rho} {kind}")
+                    d_out = fresh_out(2, n, "ca2")
+                    launch(smap, kind, 2, n, "ca2", d_in, d_out)
+                    assert same(d_out, want), (n, rho, kind)
+    finally:
+        smap.set_tile(2, "ca2", 0)
+
+
+CA3_SIZES = list(range(0, 41)) + [62, 63, 64, 65, 66, 95, 96, 97, 127, 128, 150]
+
+
+def test_ca3_parity(smap):
+    for n in CA3_SIZES:
+        inp = si.box(3, n, "bern", 3000 + n, p=0.2 if n % 2 else 0.5)
+        want = to_dev(expected(3, n, "ca3", inp))
+        d_in = to_dev(inp)
+        for kind in ("h", "bb"):
+            say(f"ca3 n={n} {kind}")
+            d_out = fresh_out(3, n, "ca3")
+            launch(smap, kind, 3, n, "ca3", d_in, d_out)
+            assert same(d_out, want), (n, kind)
+
+
+def test_ca2_two_steps_ping_pong(smap):
+    n = 700
+    a = si.box(2, n, "bern", 77, p=0.35)
+    step1 = expected(2, n, "ca2", a)
+    step2 = expected(2, n, "ca2", step1)  # outside cells of step1 hold the sentinel: never read
+    for kind in ("h", "bb"):
+        d_a, d_b = to_dev(a), to_dev(si.sentinel_box(2, n, np.uint8))
+        launch(smap, kind, 2, n, "ca2", d_a, d_b)
+        launch(smap, kind, 2, n, "ca2", d_b, d_a)
+        got = to_host(d_a, np.uint8).reshape(a.shape)
+        inside = si.inside_mask(2, n)
+        assert np.array_equal(got[inside], step2[inside])
+        assert np.array_equal(got[~inside], a[~inside])
+
+
+def test_side_stream(smap):
+    n = 1500
+    inp = si.box(2, n, "bern", 91, p=0.3)
+    want = expected(2, n, "ca2", inp)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d_in = to_dev(inp)
+        d_out = to_dev(si.sentinel_box(2, n, np.uint8))
+        smap.map_launch(2, n, "ca2", d_in, d_out, stream=s)
+    s.synchronize()
+    assert np.array_equal(to_host(d_out, np.uint8).reshape(want.shape), want)
+
+
+# --------------------------------------------------- workload sizes (sampled)
+
+def _row_inputs(m, n, dist, seed, p, rows):
+    """Full-size (lazily allocated) host box holding only the input rows the
+    oracle reads for the sampled output rows, regenerated from the seed."""
+    box = np.zeros((n + 1,) * m, dtype=np.uint8 if dist == "bern" else np.uint32)
+    need = set()
+    for hi in rows:
+        for d in np.ndindex(*(3,) * (m - 1)):
+            nb = tuple(int(h) + int(k) - 1 for h, k in zip(hi, d))
+            if min(nb) >= 0 and sum(nb) <= n:
+                need.add(nb)
+    for nb in need:
+        base = si.linear_index(m, n, (0,) + nb)
+        length = n - sum(nb) + 1
+        vals = si.values_at(seed, dist, p, np.arange(base, base + length))
+        box[tuple(reversed(nb))][:length] = vals
+    return box
+
+
+def _sample_rows(m, n, rng, k):
+    rows = set()
+    corner = [(0,) * (m - 1), (n,) + (0,) * (m - 2), (0,) * (m - 2) + (n,)]
+    for c in corner:
+        rows.add(c)
+    while len(rows) < k:
+        v = rng.integers(0, n + 1, size=m - 1)
+        if v.sum() <= n:
+            rows.add(tuple(int(a) for a in v))
+    return sorted(rows)
+
+
+def _check_outside_untouched(d, m, n, sentinel):
+    r = torch.arange(n + 1, device=d.device)
+    if m == 2:
+        mask = (r.unsqueeze(1) + r) > n
+        assert bool((d[mask] == sentinel).all())
+        return
+    s2 = r.view(-1, 1) + r
+    if m == 3:
+        for z in range(n + 1):
+            assert bool((d[z][s2 > n - z] == sentinel).all()), z
+        return
+    for w in range(n + 1):
+        for z in range(n + 1 - w if w <= n else 0):
+            assert bool((d[w, z][s2 > n - w - z] == sentinel).all()), (w, z)
+        for z in range(max(n + 1 - w, 0), n + 1):
+            assert bool((d[w, z] == sentinel).all()), (w, z)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4"])
+def test_workload_parity(smap, name):
+    w = si.WORKLOADS[name]
+    m, n, op = w["m"], w["n"], w["op"]
+    u8 = op.startswith("ca")
+    sentinel = si.SENTINEL_U8 if u8 else si.SENTINEL_U32 - (1 << 32)
+    say(f"workload {name}: m={m} n={n} op={op}")
+    d_in = None
+    if w["dist"] is not None:
+        d_in = si.box_torch(m, n, w["dist"], w["seed"], p=w["p"], device="cuda")
+    outs = {}
+    for kind, beta in kinds(m):
+        say(f"  launch {kind} beta={beta}")
+        d_out = si.sentinel_box_torch(m, n, u8)
+        launch(smap, kind, m, n, op, d_in, d_out, beta)
+        outs[(kind, beta)] = d_out
+    ref = outs[("h", 0)]
+    for key, d in outs.items():
+        assert torch.equal(d, ref), f"{key} differs from H"
+    say("  outside untouched")
+    _check_outside_untouched(ref, m, n, sentinel)
+    if name == "c1":  # small enough for the whole box
+        inp = si.box(m, n, w["dist"], w["seed"], p=w["p"])
+        want = expected(m, n, op, inp)
+        assert np.array_equal(to_host(ref, np.uint32).reshape(want.shape), want)
+        return
+    rng = np.random.default_rng(5)
+    rows = _sample_rows(m, n, rng, 48)
+    say(f"  {len(rows)} sampled rows")
+    inp = _row_inputs(m, n, w["dist"], w["seed"], w["p"], rows) if w["dist"] else None
+    for hi in rows:
+        want = oracle.row(m, n, op, inp, hi)
+        idx = tuple(reversed(hi))
+        got = ref[idx][: len(want)].cpu().numpy().view(want.dtype)
+        assert np.array_equal(got, want), (name, hi)
+    assert smap.count(m, n) == math.comb(n + m, m)
