@@ -193,8 +193,9 @@ def main():
             "ms_per_step": bb_ms, "value": useful / (bb_ms * 1e-3),
             "hbm_gbs_algorithmic": alg_bytes / (bb_ms * 1e-3) / 1e9},
         "h_vs_bb_speedup": None if bb_ms is None else bb_ms / h_ms,
-        "workgroups": {"h_launched": info_h["launched_wgs"], "bb_launched": info_bb["launched_wgs"],
-                       "useful_tiles": info_h["useful_tiles"]},
+        "tiles": {"useful": info_h["useful_tiles"], "h_launched": info_h["launched_tiles"],
+                  "bb_launched": info_bb["launched_tiles"], "wgs_per_tile": info_h["wgs_per_tile"],
+                  "h_workgroups": info_h["launched_wgs"], "bb_workgroups": info_bb["launched_wgs"]},
         "roofline": {
             "bound": "hbm" if op != "map" else "alu",
             "achieved": achieved,

@@ -85,10 +85,12 @@ struct simplex_plan_info {
     int32_t  native_n;        /* N = 2^j: the native part covers sum(b) <= N-2   */
     int32_t  shell_layers;    /* L = K - (N-1)                                   */
     int32_t  n_pieces;        /* pieces of the fused H launch (native + shell)   */
+    int32_t  wgs_per_tile;    /* workgroups per tile (row sub-blocks), >= 1      */
     uint64_t useful_elements; /* C(n+m, m)                                       */
     uint64_t useful_tiles;    /* tiles meeting the simplex: C(K-1+m, m)          */
-    uint64_t launched_wgs;    /* workgroups in the launch grid                   */
-    uint64_t native_wgs;      /* of which in the native piece (H only)           */
+    uint64_t launched_tiles;  /* tiles (map units) in the launch grid            */
+    uint64_t launched_wgs;    /* workgroups: launched_tiles * wgs_per_tile       */
+    uint64_t native_wgs;      /* tiles in the native piece (H only)              */
     uint64_t full_tiles;      /* tiles lying entirely inside the simplex         */
 };
 
@@ -134,8 +136,9 @@ int simplex_plan_info(int m, int64_t n, int r, int beta, int op, int use_bb,
  * work; the same decode functions the kernels run).  For workgroup w,
  * tiles[5w] = 1 if it maps onto a tile and 0 if it is discarded, and
  * tiles[5w+1 .. 5w+m] = its tile coordinates b_1..b_m (unused entries 0).
- * At most `cap` workgroups are written; *written receives the number of
- * workgroups of the plan.  tiles may be NULL to only query the count.
+ * At most `cap` entries are written; *written receives the number of
+ * launched tiles of the plan (the map's units; a tile may be processed by
+ * several workgroups).  tiles may be NULL to only query the count.
  */
 int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
                        int32_t *tiles, uint64_t cap, uint64_t *written);
@@ -147,9 +150,12 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
  *   MAP/ACCUM/HITS/HASH  m=2: rho 16, 32, 64, 128 (256 threads)
  *                        m=3: rho 8, 16 (256 threads)
  *                        m=4: rho 4, 8 (256 threads)
- *   CA2 (m=2): rho 64 (64 threads), 128 (128), 256 (256)
+ *   CA2 (m=2): rho 1024 (64 threads; 128 or 256), 512 (512), 256 (256),
+ *              128 (128).  A CA2 tile is split into row sub-blocks, one
+ *              workgroup each (wgs_per_tile in the plan info).
  *   CA3 (m=3): rho 32 (256 threads)
- * wg_threads = 0 picks the listed size; any other value must match it.
+ * wg_threads = 0 picks the first listed size; any other value must be one
+ * of the listed sizes.
  */
 int simplex_set_tile(int m, int op, int rho, int wg_threads);
 

@@ -43,8 +43,10 @@ class PlanInfo(ctypes.Structure):
         ("native_n", ctypes.c_int32),
         ("shell_layers", ctypes.c_int32),
         ("n_pieces", ctypes.c_int32),
+        ("wgs_per_tile", ctypes.c_int32),
         ("useful_elements", ctypes.c_uint64),
         ("useful_tiles", ctypes.c_uint64),
+        ("launched_tiles", ctypes.c_uint64),
         ("launched_wgs", ctypes.c_uint64),
         ("native_wgs", ctypes.c_uint64),
         ("full_tiles", ctypes.c_uint64),
@@ -146,7 +148,7 @@ def plan_info(m, n, op, use_bb=False, r=0, beta=0) -> dict:
 
 
 def plan_tiles(m, n, op, use_bb=False, r=0, beta=0):
-    """(valid, tiles) numpy arrays: one row per launched workgroup, in order."""
+    """(valid, tiles) numpy arrays: one row per launched tile (map unit), in order."""
     import numpy as np
     total = ctypes.c_uint64(0)
     L = lib()

@@ -5,26 +5,30 @@
 // on a triangle).
 //
 // Work split.  A workgroup owns a rho x rho tile (from H or BB).  Each lane
-// holds 4 consecutive cells of a row in one 32-bit register (SWAR bytes), so
-// a segment of rho/4 lanes covers one tile row.  A wave holds 64/(rho/4)
-// segments; every segment walks R consecutive rows of the tile downwards,
+// holds 16 consecutive cells of a row in four 32-bit registers (SWAR bytes),
+// loaded and stored as one 16-byte access, so a segment of rho/16 lanes
+// covers one tile row.  A wave holds 64/(rho/16) segments; every segment
+// walks R consecutive rows of the tile downwards,
 // keeping the horizontal 3-sums of the previous, current and next rows in
 // registers, so every input row is fetched from memory once per segment
-// (plus one halo row above and below).  The left/right neighbour bytes come
+// (plus one halo row above and below).  Rows are fetched in blocks of D so
+// that D independent loads per wave are in flight: the walk is otherwise a
+// chain of dependent row loads and runs at memory latency, not bandwidth.  The left/right neighbour bytes come
 // from the adjacent lanes through DPP wave shifts; the two halo bytes of a
 // segment come from one extra load by its first and last lane.
 //
-// Per 4 cells: h = left + centre + right (bytes, <= 3), t = h(y-1) + h(y) +
+// Per dword of 4 cells: h = left + centre + right (bytes, <= 3), t = h(y-1) + h(y) +
 // h(y+1) (<= 9, the 3x3 sum including the centre), next = (t == 3) |
 // (alive & t == 4).  Byte-wise equality uses ((t ^ k) + 0x7F) & 0x80, which
 // cannot carry between bytes because every byte is below 0x80.
 //
-// Boundary handling.  Rows whose whole segment (with halo) lies inside the
-// simplex load and store plain dwords.  Other rows zero the cells outside
-// the simplex or the box after loading (the input there is arbitrary),
-// never load a dword that holds no simplex cell, and store only the cells
-// inside (byte stores for the last partial dword).  Rows are unaligned
-// (pitch n+1); gfx9 global loads and stores accept unaligned dwords.
+// Boundary handling is per lane: a lane whose 16 cells are inside loads
+// and stores them as one (unaligned; gfx9 global memory accepts unaligned
+// accesses) 16-byte access; the lane the hypotenuse cuts zeroes the bytes
+// outside after loading (the input there is arbitrary) and stores only the
+// cells inside; lanes beyond it touch nothing.  No access ever covers a
+// dword without a simplex cell, except the tail bytes of a 16-byte load
+// that stays inside the buffer.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -85,94 +89,198 @@ __device__ __forceinline__ uint32_t life_b3s23(uint32_t t, uint32_t c)
     return ((~ne3 | (~ne4 & (c << 7))) >> 7) & 0x01010101u;
 }
 
-// left + centre + right neighbours, bytewise, from the lane's dword c, the
-// adjacent lanes' dwords (DPP) and the segment's halo dword e.
-template <int S>
-__device__ __forceinline__ uint32_t hsum3(uint32_t c, uint32_t e, int sl)
+// Sum of left, centre and right neighbours of the 16 cells c[0..3] of a lane
+// (c[0] lowest addresses), given the dword just before c[0] (lprev) and the
+// dword just after c[3] (rnext).
+__device__ __forceinline__ void hsum16(const uint32_t *c, uint32_t lprev, uint32_t rnext, uint32_t *h)
 {
-    uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)c, 0x138, 0xf, 0xf, false);  // wave_shr:1
-    uint32_t r = (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)c, 0x130, 0xf, 0xf, false);  // wave_shl:1
-    if (sl == 0) l = e;
-    if (sl == S - 1) r = e;
-    return __builtin_amdgcn_alignbyte(c, l, 3) + c + __builtin_amdgcn_alignbyte(r, c, 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t l = i == 0 ? lprev : c[i - 1];
+        const uint32_t r = i == 3 ? rnext : c[i + 1];
+        h[i] = __builtin_amdgcn_alignbyte(c[i], l, 3) + c[i] + __builtin_amdgcn_alignbyte(r, c[i], 1);
+    }
 }
 
-template <int RHO, int W, bool BB>
+// The neighbouring lanes' boundary dwords (DPP) or, at a segment edge, the
+// halo dword e.  Written as value selects: conditional writes through
+// references here were turned into a dynamically addressed scratch store.
+template <int S>
+__device__ __forceinline__ uint32_t lane_prev(const uint32_t *c, uint32_t e, int sl)
+{
+    const uint32_t d = (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)c[3], 0x138, 0xf, 0xf, false);  // wave_shr:1
+    return sl == 0 ? e : d;
+}
+template <int S>
+__device__ __forceinline__ uint32_t lane_next(const uint32_t *c, uint32_t e, int sl)
+{
+    const uint32_t d = (uint32_t)__builtin_amdgcn_update_dpp((int)e, (int)c[0], 0x130, 0xf, 0xf, false);  // wave_shl:1
+    return sl == S - 1 ? e : d;
+}
+
+// One Life step of a rho x rho tile.  Each lane holds 16 cells of a row
+// (one unaligned 16-byte access, four SWAR dwords); a segment of rho/16
+// lanes covers a tile row; each segment walks R rows.  A tile is split into
+// SUB = rho / (W * SEGS * R) sub-blocks of rows, one workgroup each (the
+// launch grid is the map's grid times SUB, sub-blocks of a tile adjacent).
+template <int RHO, int W, int R, int D, bool BB, bool SAFE>
 __global__ __launch_bounds__(64 * W) void k_ca2(const Plan P, const uint8_t *__restrict__ in,
                                                 uint8_t *__restrict__ out)
 {
-    constexpr int S = RHO / 4;         // lanes per tile row
-    constexpr int SEGS = 64 / S;       // row segments per wave
-    constexpr int R = RHO / (W * SEGS);  // rows walked by each segment
-    static_assert(S >= 2 && S <= 64 && 64 % S == 0 && R >= 1, "bad CA2 tile shape");
+    constexpr int S = RHO / 16;          // lanes per tile row
+    constexpr int SEGS = 64 / S;         // row segments per wave
+    constexpr int SUB = RHO / (W * SEGS * R);
+    static_assert(S >= 2 && S <= 64 && 64 % S == 0 && R >= 1 && SUB >= 1 &&
+                  SUB * W * SEGS * R == RHO && (SUB & (SUB - 1)) == 0, "bad CA2 tile shape");
 
     int32_t t[4] = {0, 0, 0, 0};
-    if (!wg_tile<2, BB>(P, t)) return;
+    uint32_t sub;
+    if (BB) {
+        decode_bb(P, blockIdx.x, blockIdx.y / SUB, 0, t);
+        sub = blockIdx.y % SUB;
+    } else {
+        if (!decode_h<2>(P, blockIdx.x / SUB, t)) return;
+        sub = blockIdx.x % SUB;
+    }
     const int32_t n = P.n;
-    const int32_t x0 = t[0] * RHO, y0 = t[1] * RHO;
+    const int32_t x0 = t[0] * RHO, y0 = t[1] * RHO + (int32_t)sub * (W * SEGS * R);
     if (x0 + y0 > n) return;
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // scalar
     const int seg = lane / S, sl = lane % S;
     const int32_t ywave = y0 + wave * SEGS * R;   // first row of the wave's first segment
-    const int32_t ybeg = ywave + seg * R;          // first row of this lane's segment
-    // rows after n - x0 hold no simplex cell in this tile column
+    // rows after n - x0 hold no simplex cell in this tile column (wave-uniform)
     const int32_t rows = min(R, n - x0 - ywave + 1);
     if (rows <= 0) return;                          // whole wave idle (no barriers here)
 
     const int64_t pitch = P.stride[1];
     const int64_t total = pitch * pitch;
-    const int32_t x = x0 + 4 * sl;
-    const bool has_e = (sl == 0) || (sl == S - 1);
+    const int32_t x = x0 + 16 * sl;
     const int32_t xe = (sl == 0) ? x0 - 4 : x0 + RHO;
-    const bool left_ok = x0 >= 4;
+    const bool is_edge = (sl == 0) || (sl == S - 1);
+    // Row r of the wave (r = -1 .. R) is addressed as a wave-uniform row
+    // pointer (scalar) plus a per-lane 32-bit offset that is the same for
+    // every row: the segment's row offset plus the column.  The halo offset
+    // of a lane that never loads it is clamped to 0 (offsets are unsigned).
+    const uint32_t seg_off = (uint32_t)(seg * R) * (uint32_t)pitch;
+    const uint32_t off_c = seg_off + (uint32_t)x;
+    const uint32_t off_e = seg_off + (uint32_t)max(xe, 0);
+    const int32_t lane_rows = seg * R;             // the lane's row is ywave + r + lane_rows
 
-    // Load row y of this segment: own dword and (first/last lane) halo dword.
-    // `fast` is wave-uniform: every row the wave touches at this step lies
-    // inside the simplex with its halo.
-    auto load_row = [&](int32_t y, bool fast, uint32_t &c, uint32_t &e) {
+    // Rows with a simplex cell in this lane: 0 <= y <= n and x <= n - y.
+    // For n >= 15 a 16-byte access starting at such a cell never passes the
+    // end of the buffer (worst case y = n, x = 0: n (n+1) + 16 <= (n+1)^2),
+    // and neither does the 4-byte halo access; the host launches the SAFE
+    // instantiation (byte-safe loads through ld_masked) for smaller n.
+    constexpr bool safe = SAFE;
+
+    // Raw loads of wave row r: the lane's 16 cells (if any is in the
+    // simplex) and its halo dword (first/last lane of a segment).  No masking
+    // here, so the loads of a block issue back to back.
+    auto load_raw = [&](int32_t r, uint32_t *c, uint32_t &e) {
+        c[0] = c[1] = c[2] = c[3] = 0u;
+        e = 0u;
+        const int32_t y = ywave + r + lane_rows;
+        if ((uint32_t)y > (uint32_t)n) return;      // y < 0 or y > n
+        const uint8_t *rowp = in + (int64_t)(ywave + r) * pitch;   // wave-uniform
+        if (x <= n - y) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(rowp + off_c);
+            c[0] = q.x; c[1] = q.y; c[2] = q.z; c[3] = q.w;
+        }
+        if (is_edge && xe >= 0 && xe <= n - y) e = ld_u32(rowp + off_e);
+    };
+    // Zero the cells of wave row r that lie outside the simplex (only the
+    // lane the hypotenuse cuts, and the right halo byte, can hold any).
+    auto mask_row = [&](int32_t r, uint32_t *c, uint32_t &e) {
+        const int32_t y = ywave + r + lane_rows;
+        const int32_t v = n - y - x + 1;             // simplex cells from x on
+        if (v < 16) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int32_t keep = v - 4 * i;
+                c[i] = keep >= 4 ? c[i] : (keep <= 0 ? 0u : c[i] & ((1u << (8 * keep)) - 1u));
+            }
+        }
+        const int32_t ve = n - y - xe + 1;
+        if (ve < 4) e = ve <= 0 ? 0u : e & ((1u << (8 * ve)) - 1u);
+    };
+    // Byte-safe load of wave row r for tiny n.
+    auto load_safe = [&](int32_t r, uint32_t *c, uint32_t &e) {
+        c[0] = c[1] = c[2] = c[3] = 0u;
+        e = 0u;
+        const int32_t y = ywave + r + lane_rows;
+        if ((uint32_t)y > (uint32_t)n) return;
         const int64_t rb = (int64_t)y * pitch;
-        if (fast) {
-            c = ld_u32(in + rb + x);
-            e = has_e ? ld_u32(in + rb + xe) : 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = ld_masked(in + rb, x + 4 * i, y, n, total - rb);
+        if (is_edge) e = ld_masked(in + rb, xe, y, n, total - rb);
+    };
+    auto store_row = [&](int32_t r, const uint32_t *res) {
+        const int32_t y = ywave + r + lane_rows;
+        if ((uint32_t)y > (uint32_t)n) return;
+        const int32_t v = n - y - x + 1;
+        if (v <= 0) return;
+        if (v >= 16) {
+            uint8_t *rowp = out + (int64_t)(ywave + r) * pitch;    // wave-uniform
+            *reinterpret_cast<uint4 *>(rowp + off_c) = make_uint4(res[0], res[1], res[2], res[3]);
         } else {
-            const bool yin = (y >= 0) && (y <= n);
-            const uint8_t *row = in + (yin ? rb : 0);
-            const int64_t room = total - (yin ? rb : 0);
-            c = yin ? ld_masked(row, x, y, n, room) : 0u;
-            e = (yin && has_e) ? ld_masked(row, xe, y, n, room) : 0u;
+            uint8_t *row = out + (int64_t)y * pitch;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) st_masked(row, x + 4 * i, y, n, res[i]);
         }
     };
-    auto fast_at = [&](int32_t r) {  // rows ywave + r + seg * R for all segments
-        const int32_t ylo = ywave + r, yhi = ywave + (SEGS - 1) * R + r;
-        return left_ok && ylo >= 0 && (x0 + RHO + yhi <= n);
+    auto load_row = [&](int32_t r, uint32_t *c, uint32_t &e) {
+        if constexpr (SAFE) {
+            load_safe(r, c, e);
+        } else {
+            load_raw(r, c, e);
+            mask_row(r, c, e);
+        }
     };
 
-    uint32_t ca, ea, cb, eb, cn, en;
-    load_row(ybeg - 1, fast_at(-1), ca, ea);
-    load_row(ybeg, fast_at(0), cb, eb);
-    load_row(ybeg + 1, fast_at(1), cn, en);
-    uint32_t hp = hsum3<S>(ca, ea, sl);
-    uint32_t hc = hsum3<S>(cb, eb, sl);
-    uint32_t cc = cb;
+    // Prologue: the row above the segment and its first row.
+    uint32_t hp[4], hc[4], cc[4];
+    {
+        uint32_t ca[4], ea, eb;
+        load_row(-1, ca, ea);
+        load_row(0, cc, eb);
+        hsum16(ca, lane_prev<S>(ca, ea, sl), lane_next<S>(ca, ea, sl), hp);
+        hsum16(cc, lane_prev<S>(cc, eb, sl), lane_next<S>(cc, eb, sl), hc);
+    }
 
-    for (int32_t r = 0; r < rows; ++r) {
-        uint32_t cnn = 0u, enn = 0u;
-        if (r + 2 <= rows) load_row(ybeg + r + 2, fast_at(r + 2), cnn, enn);
-        const uint32_t hn = hsum3<S>(cn, en, sl);
-        const uint32_t res = life_b3s23(hp + hc + hn, cc);
-        const int32_t y = ybeg + r;
-        if (fast_at(r)) {
-            st_u32(out + (int64_t)y * pitch + x, res);
-        } else if (y <= n) {
-            st_masked(out + (int64_t)y * pitch, x, y, n, res);
+    // Blocks of D output rows: issue the D row loads the block needs (rows
+    // r0+1 .. r0+D, independent, so D rows per wave are in flight), then
+    // mask, sum and store.  `rows` is wave-uniform, so the guards are scalar
+    // branches.
+    for (int32_t r0 = 0; r0 < rows; r0 += D) {
+        uint32_t cn[D][4], en[D];
+        if constexpr (SAFE) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) load_safe(r0 + 1 + k, cn[k], en[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < D; ++k) load_raw(r0 + 1 + k, cn[k], en[k]);
         }
-        hp = hc;
-        hc = hn;
-        cc = cn;
-        cn = cnn;
-        en = enn;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if constexpr (!SAFE) mask_row(r0 + 1 + k, cn[k], en[k]);
+            if (r0 + 1 + k > rows) {  // below the segment's last needed row
+                cn[k][0] = cn[k][1] = cn[k][2] = cn[k][3] = 0u;
+                en[k] = 0u;
+            }
+            uint32_t hn[4], res[4];
+            hsum16(cn[k], lane_prev<S>(cn[k], en[k], sl), lane_next<S>(cn[k], en[k], sl), hn);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) res[i] = life_b3s23(hp[i] + hc[i] + hn[i], cc[i]);
+            if (r0 + k < rows) store_row(r0 + k, res);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                hp[i] = hc[i];
+                hc[i] = hn[i];
+                cc[i] = cn[k][i];
+            }
+        }
     }
 }
 

@@ -158,20 +158,34 @@ SMAP_HD bool h3_native(int j, uint32_t w, int32_t *t)
 // Level-ordered 4-D map with replication beta (3: hinge, 4: none).
 SMAP_HD bool h4_native(const Plan &P, uint32_t w, int32_t *t)
 {
+    // level: last l with lvl_start[l] <= w (unrolled: no runtime-indexed reads)
     int l = 0;
-    while (l + 1 < P.nlvl && w >= P.lvl_start[l + 1]) ++l;
-    const uint32_t i = w - P.lvl_start[l];
+    uint32_t start = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxLevels; ++k) {
+        if (k < P.nlvl && w >= P.lvl_start[k]) {
+            l = k;
+            start = P.lvl_start[k];
+        }
+    }
+    const uint32_t i = w - start;
     const uint32_t lc = (uint32_t)(P.j - 1 - l);
     const uint32_t c = 1u << lc;
     const uint32_t cell = i & ((1u << (4u * lc)) - 1u);
     uint32_t q = i >> (4u * lc);
     int32_t lam[4], o[4] = {0, 0, 0, 0};
+#pragma unroll
     for (int k = 0; k < 4; ++k) lam[k] = (int32_t)((cell >> (uint32_t(k) * lc)) & (c - 1u));
     const uint32_t beta = (uint32_t)P.beta;
     for (int k = l; k >= 1; --k) {                // corner chosen at depth k
         const uint32_t d = q % beta;
         q /= beta;
-        o[d] += (int32_t)((1u << P.j) >> k);
+        const int32_t step = (int32_t)((1u << P.j) >> k);
+        // select the axis without a dynamically indexed array (no scratch)
+        o[0] += d == 0u ? step : 0;
+        o[1] += d == 1u ? step : 0;
+        o[2] += d == 2u ? step : 0;
+        o[3] += d == 3u ? step : 0;
     }
     const int32_t ci = (int32_t)c;
     const int32_t s = lam[0] + lam[1] + lam[2] + lam[3];
@@ -189,40 +203,63 @@ SMAP_HD bool h4_native(const Plan &P, uint32_t w, int32_t *t)
 
 // ---- H: native + shell pieces ------------------------------------------------
 
+template <int M>
 SMAP_HD bool decode_h(const Plan &P, uint32_t w, int32_t *t)
 {
-    const int m = P.m;
+    constexpr int m = M;
+    // piece: last p with piece_start[p] <= w (unrolled: no runtime-indexed reads)
     int p = 0;
-    while (p + 1 < P.npieces && w >= P.piece_start[p + 1]) ++p;
-    const uint32_t loc = w - P.piece_start[p];
+    uint32_t pstart = 0, bc = P.base_count[0];
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+        if (k < P.npieces && w >= P.piece_start[k]) {
+            p = k;
+            pstart = P.piece_start[k];
+            bc = P.base_count[k];
+        }
+    }
+    const uint32_t loc = w - pstart;
     if (p == 0) {
-        if (m == 2) { h2_native(P.j, loc, t); return true; }
-        if (m == 3) return h3_native(P.j, loc, t);
-        return h4_native(P, loc, t);
+        if constexpr (M == 2) { h2_native(P.j, loc, t); return true; }
+        else if constexpr (M == 3) return h3_native(P.j, loc, t);
+        else return h4_native(P, loc, t);
     }
     const int d = m - p;                          // base dimension of this piece
-    const uint32_t bc = P.base_count[p];
     const uint32_t base = loc % bc;
     uint32_t lay = loc / bc;
     if (d == 1) {
         t[0] = (int32_t)base;
     } else if (d == 2) {
         h2_native(P.j, base, t);
-    } else {
+    } else if constexpr (M == 4) {
         if (!h3_native(P.j, base, t)) return false;
     }
     const int32_t h = (1 << P.j) - 1;
-    int32_t s = 0;
-    for (int k = 0; k < d; ++k) s += t[k];
     const uint32_t L = (uint32_t)P.L;
-    for (int k = d; k < m; ++k) {
-        const int32_t ik = (int32_t)(lay % L);
-        lay /= L;
-        t[k] = h + ik - s;
-        if (t[k] < 0) return false;
-        s = h + ik;
+    // Compile-time indices only (the coordinates stay in registers).
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < d) s += t[k];
+    bool ok = true;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        if (k >= d && k < m) {
+            const int32_t ik = (int32_t)(lay % L);
+            lay /= L;
+            t[k] = h + ik - s;
+            ok = ok && t[k] >= 0;
+            s = h + ik;
+        }
     }
-    return true;
+    return ok;
+}
+
+SMAP_HD bool decode_h_rt(const Plan &P, uint32_t w, int32_t *t)  // host-side dispatch on m
+{
+    if (P.m == 2) return decode_h<2>(P, w, t);
+    if (P.m == 3) return decode_h<3>(P, w, t);
+    return decode_h<4>(P, w, t);
 }
 
 // ---- BB ---------------------------------------------------------------------

@@ -23,6 +23,16 @@ namespace {
 struct TileCfg {
     int rho;
     int wg;
+    int sub;  // workgroups per tile (CA2 splits a tile into row sub-blocks)
+};
+
+// CA2 shapes: (rho, threads) -> waves W, rows per wave R, sub-blocks per tile.
+struct Ca2Shape {
+    int rho, wg, w, r, sub;
+};
+constexpr Ca2Shape kCa2Shapes[] = {
+    {1024, 64, 1, 16, 64}, {1024, 128, 2, 16, 32}, {1024, 256, 4, 16, 16},
+    {512, 512, 8, 16, 2},  {256, 256, 4, 16, 1},   {128, 128, 2, 8, 1},
 };
 
 // op class: 0 = pointwise (MAP/ACCUM/HITS/HASH), 1 = CA2, 2 = CA3
@@ -30,25 +40,30 @@ int op_class(int op) { return op == OP_CA2 ? 1 : (op == OP_CA3 ? 2 : 0); }
 
 TileCfg default_tile(int m, int cls)
 {
-    if (cls == 1) return {256, 256};
-    if (cls == 2) return {32, 256};
-    if (m == 2) return {32, 256};
-    if (m == 3) return {8, 256};
-    return {4, 256};
+    if (cls == 1) return {1024, 64, 64};
+    if (cls == 2) return {32, 256, 1};
+    if (m == 2) return {32, 256, 1};
+    if (m == 3) return {8, 256, 1};
+    return {4, 256, 1};
 }
 
-bool tile_supported(int m, int cls, int rho, int *wg)
+bool tile_supported(int m, int cls, int rho, int *wg, int *sub)
 {
+    *sub = 1;
     if (cls == 0) {
         *wg = 256;
         if (m == 2) return rho == 16 || rho == 32 || rho == 64 || rho == 128;
         if (m == 3) return rho == 8 || rho == 16;
         return rho == 4 || rho == 8;
     }
-    if (cls == 1) {
-        if (rho == 64) { *wg = 64; return true; }
-        if (rho == 128) { *wg = 128; return true; }
-        if (rho == 256) { *wg = 256; return true; }
+    if (cls == 1) {  // the first listed shape of a rho is its default
+        for (const Ca2Shape &c : kCa2Shapes) {
+            if (c.rho == rho && (*wg == 0 || *wg == c.wg)) {
+                *wg = c.wg;
+                *sub = c.sub;
+                return true;
+            }
+        }
         return false;
     }
     *wg = 256;
@@ -108,6 +123,10 @@ int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C
     if (it == g_plans.end()) {
         CachedPlan cp{};
         cp.status = make_plan(m, n, beta, t.rho, bb, &cp.plan, &cp.counts);
+        if (cp.status == kOk && !bb && (uint64_t)cp.plan.total * (uint64_t)t.sub > kMaxWorkgroups)
+            cp.status = kErange;
+        if (cp.status == kOk && bb && m == 2 && (uint64_t)cp.plan.kbox * (uint64_t)t.sub > 65535)
+            cp.status = kErange;
         if (cp.status == kOk) {
             // largest offset inside one tile, in bytes (uint32 elements)
             __int128 span = 0;
@@ -195,19 +214,32 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P, const void *in, vo
              hipStream_t s)
 {
     dim3 grid;
+    const uint32_t sub = (uint32_t)tc.sub;
     if (BB) {
         const uint32_t kb = (uint32_t)P.kbox;
-        grid = (m == 2) ? dim3(kb, kb, 1) : (m == 3 ? dim3(kb, kb, kb) : dim3(kb, kb, kb * kb));
+        grid = (m == 2) ? dim3(kb, kb * sub, 1) : (m == 3 ? dim3(kb, kb, kb) : dim3(kb, kb, kb * kb));
     } else {
-        grid = dim3(P.total, 1, 1);
+        grid = dim3(P.total * sub, 1, 1);
     }
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
         uint8_t *o8 = (uint8_t *)out;
-        switch (tc.rho) {
-        case 64: hipLaunchKernelGGL((k_ca2<64, 1, BB>), grid, dim3(64), 0, s, P, i8, o8); return kOk;
-        case 128: hipLaunchKernelGGL((k_ca2<128, 2, BB>), grid, dim3(128), 0, s, P, i8, o8); return kOk;
-        case 256: hipLaunchKernelGGL((k_ca2<256, 4, BB>), grid, dim3(256), 0, s, P, i8, o8); return kOk;
+        constexpr int D = 2;  // rows in flight per wave (more costs occupancy)
+        switch (tc.rho * 10000 + tc.wg) {
+#define SMAP_CA2(RHO, WG, W, R)                                                                  \
+        case RHO * 10000 + WG:                                                                    \
+            if (P.n < 15)                                                                         \
+                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, true>), grid, dim3(WG), 0, s, P, i8, o8); \
+            else                                                                                  \
+                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, false>), grid, dim3(WG), 0, s, P, i8, o8); \
+            return kOk;
+        SMAP_CA2(1024, 64, 1, 16)
+        SMAP_CA2(1024, 128, 2, 16)
+        SMAP_CA2(1024, 256, 4, 16)
+        SMAP_CA2(512, 512, 8, 16)
+        SMAP_CA2(256, 256, 4, 16)
+        SMAP_CA2(128, 128, 2, 8)
+#undef SMAP_CA2
         }
         return kEunsupported;
     }
@@ -296,7 +328,9 @@ int simplex_plan_info(int m, int64_t n, int r, int beta, int op, int use_bb,
     info.n_pieces = use_bb ? 1 : P.npieces;
     if (!binom_u64((uint64_t)n + m, (uint64_t)m, &info.useful_elements)) return kErange;
     info.useful_tiles = C.useful_tiles;
-    info.launched_wgs = C.launched;
+    info.launched_tiles = C.launched;
+    info.wgs_per_tile = tc.sub;
+    info.launched_wgs = C.launched * (uint64_t)tc.sub;
     info.native_wgs = C.native;
     info.full_tiles = C.full_tiles;
     *out = info;
@@ -332,7 +366,7 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb, in
             for (int k = 0; k < m; ++k) s += (int64_t)t[k] * tc.rho;
             ok = s <= n;
         } else {
-            ok = decode_h(P, (uint32_t)w, t);
+            ok = decode_h_rt(P, (uint32_t)w, t);
         }
         int32_t *o = tiles + 5 * w;
         o[0] = ok ? 1 : 0;
@@ -351,10 +385,10 @@ int simplex_set_tile(int m, int op, int rho, int wg_threads)
         g_tiles.erase({m, cls});
         return kOk;
     }
-    int wg = 0;
-    if (!tile_supported(m, cls, rho, &wg)) return kEunsupported;
+    int wg = wg_threads, sub = 1;
+    if (!tile_supported(m, cls, rho, &wg, &sub)) return kEunsupported;
     if (wg_threads != 0 && wg_threads != wg) return kEunsupported;
-    g_tiles[{m, cls}] = TileCfg{rho, wg};
+    g_tiles[{m, cls}] = TileCfg{rho, wg, sub};
     return kOk;
 }
 

@@ -54,7 +54,7 @@ __device__ __forceinline__ bool wg_tile(const Plan &P, int32_t *t)
         decode_bb(P, blockIdx.x, blockIdx.y, blockIdx.z, t);
         return true;
     }
-    return decode_h(P, blockIdx.x, t);
+    return decode_h<M>(P, blockIdx.x, t);
 }
 
 template <int M, int RHO, int OP, bool BB>

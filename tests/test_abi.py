@@ -94,21 +94,28 @@ def test_set_tile_validation():
     with pytest.raises(smap.SimplexMapError):
         smap.set_tile(2, "accum", 24)
     with pytest.raises(smap.SimplexMapError):
-        smap.set_tile(2, "ca2", 256, wg_threads=64)
+        smap.set_tile(2, "ca2", 256, wg_threads=512)
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_tile(2, "ca2", 64)
     with pytest.raises(smap.SimplexMapError):
         smap.set_tile(3, "ca3", 16)
-    smap.set_tile(2, "ca2", 64)
-    assert smap.plan_info(2, 1000, "ca2")["rho"] == 64
-    assert smap.plan_info(2, 1000, "ca2")["wg_threads"] == 64
+    smap.set_tile(2, "ca2", 128)
+    assert smap.plan_info(2, 1000, "ca2")["rho"] == 128
+    assert smap.plan_info(2, 1000, "ca2")["wg_threads"] == 128
+    smap.set_tile(2, "ca2", 1024, 256)
+    info = smap.plan_info(2, 16384, "ca2")
+    assert info["wg_threads"] == 256 and info["wgs_per_tile"] == 16
+    assert info["launched_wgs"] == 16 * info["launched_tiles"]
     smap.set_tile(2, "ca2", 0)
-    assert smap.plan_info(2, 1000, "ca2")["rho"] == 256
+    info = smap.plan_info(2, 16384, "ca2")
+    assert info["rho"] == 1024 and info["wg_threads"] == 64 and info["wgs_per_tile"] == 64
 
 
 def test_plan_info_fields():
     info = smap.plan_info(2, 16384, "ca2")
     assert info["useful_elements"] == 134242305
-    assert info["tile_side_k"] == 65 and info["native_n"] == 64 and info["shell_layers"] == 2
+    assert info["tile_side_k"] == 17 and info["native_n"] == 16 and info["shell_layers"] == 2
     bb = smap.plan_info(2, 16384, "ca2", use_bb=True)
-    assert bb["launched_wgs"] == 65 * 65 and bb["use_bb"] == 1
+    assert bb["launched_tiles"] == 17 * 17 and bb["use_bb"] == 1
     assert smap.plan_info(4, 128, "hash")["beta"] == 3
     assert smap.plan_info(4, 128, "hash", beta=4)["beta"] == 4

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 POINT_TILES = {2: [16, 32, 64, 128], 3: [8, 16], 4: [4, 8]}
-CA2_TILES = [64, 128, 256]
+CA2_TILES = [(1024, 64), (1024, 128), (1024, 256), (512, 512), (256, 256), (128, 128)]
 
 
 def say(*a):
@@ -151,13 +151,13 @@ def test_ca2_parity(smap):
             inp = si.box(2, n, "bern", 2000 + n, p=0.3)
             want = to_dev(expected(2, n, "ca2", inp))
             d_in = to_dev(inp)
-            for rho in CA2_TILES:
-                smap.set_tile(2, "ca2", rho)
+            for rho, wg in CA2_TILES:
+                smap.set_tile(2, "ca2", rho, wg)
                 for kind in ("h", "bb"):
-                    say(f"ca2 n={n} rho={rho} {kind}")
+                    say(f"ca2 n={n} rho={rho} wg={wg} {kind}")
                     d_out = fresh_out(2, n, "ca2")
                     launch(smap, kind, 2, n, "ca2", d_in, d_out)
-                    assert same(d_out, want), (n, rho, kind)
+                    assert same(d_out, want), (n, rho, wg, kind)
     finally:
         smap.set_tile(2, "ca2", 0)
 

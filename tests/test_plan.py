@@ -24,7 +24,7 @@ TILES = {  # (m, op) -> supported rho values
     (2, "hits"): [16, 32, 64, 128],
     (3, "hits"): [8, 16],
     (4, "hits"): [4, 8],
-    (2, "ca2"): [64, 128, 256],
+    (2, "ca2"): [128, 256, 512, 1024],
     (3, "ca3"): [32],
 }
 
@@ -34,7 +34,7 @@ def check_exact(m, n, op, use_bb=False, beta=0):
     rho = info["rho"]
     M = n // rho
     valid, tiles = smap.plan_tiles(m, n, op, use_bb=use_bb, beta=beta)
-    assert len(valid) == info["launched_wgs"]
+    assert len(valid) == info["launched_tiles"]
     t = tiles[valid].astype(np.int64)
     assert np.all(t >= 0)
     assert np.all(t.sum(axis=1) <= M)
@@ -69,7 +69,7 @@ def test_bb_covers_block_simplex_exactly_once(m, op):
                 smap.plan_info(m, n, op, use_bb=True)
             continue
         info = check_exact(m, n, op, use_bb=True)
-        assert info["launched_wgs"] == ((n + info["rho"]) // info["rho"]) ** m
+        assert info["launched_tiles"] == ((n + info["rho"]) // info["rho"]) ** m
 
 
 @pytest.mark.parametrize("m,n,op,beta", [(2, 1024, "accum", 0), (2, 16384, "ca2", 0),
@@ -108,13 +108,13 @@ def test_native_counts_match_closed_forms():
             n = 16 * (N - 2)
             info = smap.plan_info(2, n, "hits")
             assert info["shell_layers"] == 0 and info["native_n"] == N
-            assert info["launched_wgs"] == N * (N - 1) // 2          # eq_m2
-            assert info["launched_wgs"] == info["useful_tiles"]       # no waste in 2-D
+            assert info["launched_tiles"] == N * (N - 1) // 2          # eq_m2
+            assert info["launched_tiles"] == info["useful_tiles"]       # no waste in 2-D
         for j in range(1, 8):
             N = 1 << j
             info = smap.plan_info(3, 8 * (N - 2), "hits")
             assert info["native_n"] == N and info["shell_layers"] == 0
-            assert info["launched_wgs"] == (N // 2) ** 2 * (N // 2 + N // 4)
+            assert info["launched_tiles"] == (N // 2) ** 2 * (N // 2 + N // 4)
             assert info["useful_tiles"] == (N ** 3 - N) // 6          # eq_m3
         for j in range(1, 6):
             N = 1 << j
@@ -122,7 +122,7 @@ def test_native_counts_match_closed_forms():
                 info = smap.plan_info(4, 4 * (N - 2), "hits", beta=beta)
                 assert info["native_n"] == N and info["shell_layers"] == 0
                 # eq_generic-m with r = 1/2
-                assert info["launched_wgs"] * (16 - beta) == N ** 4 - beta ** j
+                assert info["launched_tiles"] * (16 - beta) == N ** 4 - beta ** j
     finally:
         for m in (2, 3, 4):
             smap.set_tile(m, "hits", 0)
@@ -136,7 +136,7 @@ def test_packed_3d_grid_ratio_tends_to_nine_eighths():
         for j in (4, 6, 8):
             N = 1 << j
             info = smap.plan_info(3, 8 * (N - 2), "hits")
-            ratios.append(info["launched_wgs"] / info["useful_tiles"])
+            ratios.append(info["launched_tiles"] / info["useful_tiles"])
         assert ratios[0] > ratios[1] > ratios[2] > 1.125
         assert abs(ratios[2] - 1.125) < 0.002
     finally:
@@ -149,7 +149,7 @@ def test_bb_ratio_tends_to_m_factorial():
         smap.set_tile(m, "hits", {2: 16, 3: 8, 4: 4}[m])
         try:
             info = smap.plan_info(m, n, "hits", use_bb=True)
-            ratio = info["launched_wgs"] / info["useful_tiles"]
+            ratio = info["launched_tiles"] / info["useful_tiles"]
             assert abs(ratio / math.factorial(m) - 1) < 0.25
         finally:
             smap.set_tile(m, "hits", 0)
@@ -166,7 +166,7 @@ def test_theorem1_worked_case():
     try:
         n = 16 * 2  # floor(n / rho) = 2, K = 3 = N - 1 with N = 4: native map only
         info = smap.plan_info(2, n, "hits")
-        assert info["native_n"] == 4 and info["shell_layers"] == 0 and info["launched_wgs"] == 6
+        assert info["native_n"] == 4 and info["shell_layers"] == 0 and info["launched_tiles"] == 6
         valid, tiles = smap.plan_tiles(2, n, "hits")
         assert valid.all()
         for wx, wy, X, Y in rows:
