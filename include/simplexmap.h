@@ -147,13 +147,16 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
  * Select the tile side rho and workgroup size for (m, op) in later calls of
  * this process (both launch kinds).  rho = 0 restores the default.  Only
  * the compiled combinations are accepted (others: SMAP_EUNSUPPORTED):
- *   MAP/ACCUM/HITS/HASH  m=2: rho 16, 32, 64, 128 (256 threads)
- *                        m=3: rho 8, 16 (256 threads)
- *                        m=4: rho 4, 8 (256 threads)
+ *   MAP/ACCUM/HITS/HASH  m=2: rho 32 (256 threads), 16 (64), 64 (256), 128 (256)
+ *                        m=3: rho 16 (256), 8 (128), 32 (256)
+ *                        m=4: rho 8 (256), 4 (64), 16 (256)
+ *                        (the first listed rho of each m is the default)
  *   CA2 (m=2): rho 1024 (64 threads; 128 or 256), 512 (512), 256 (256),
- *              128 (128).  A CA2 tile is split into row sub-blocks, one
- *              workgroup each (wgs_per_tile in the plan info).
- *   CA3 (m=3): rho 32 (256 threads)
+ *              128 (128).
+ *   Large tiles are split into sub-blocks of rows (and planes), one
+ *   workgroup each (wgs_per_tile in the plan info).
+ *   CA3 (m=3): rho 128 (256 threads; 128 or 64), 256 (256), 64 (128 or 64),
+ *              32 (64).
  * wg_threads = 0 picks the first listed size; any other value must be one
  * of the listed sizes.
  */

@@ -19,8 +19,8 @@
 //
 // Per dword of 4 cells: h = left + centre + right (bytes, <= 3), t = h(y-1) + h(y) +
 // h(y+1) (<= 9, the 3x3 sum including the centre), next = (t == 3) |
-// (alive & t == 4).  Byte-wise equality uses ((t ^ k) + 0x7F) & 0x80, which
-// cannot carry between bytes because every byte is below 0x80.
+// (alive & t == 4), evaluated byte-wise with bit-7 tests that cannot carry
+// between bytes (see life_b3s23).
 //
 // Boundary handling is per lane: a lane whose 16 cells are inside loads
 // and stores them as one (unaligned; gfx9 global memory accepts unaligned
@@ -81,12 +81,15 @@ __device__ __forceinline__ void st_masked(uint8_t *row, int32_t x, int32_t r, in
     }
 }
 
-// Life B3/S23 on four byte cells: t = 3x3 sum including the centre.
+// Life B3/S23 on four byte cells: t = 3x3 sum including the centre (<= 9),
+// c = centre (0/1).  next = 1 iff t >= 3 and t - 3 <= c.  With d = t + 0x7D
+// per byte, bit 7 of d is (t >= 3); e = d - (c + 1) has bit 7 clear iff
+// t - 3 <= c (no byte borrows or carries: 0x7B <= e, d <= 0x86).
 __device__ __forceinline__ uint32_t life_b3s23(uint32_t t, uint32_t c)
 {
-    const uint32_t ne3 = (t ^ 0x03030303u) + 0x7F7F7F7Fu;  // bit 7 set where t != 3
-    const uint32_t ne4 = (t ^ 0x04040404u) + 0x7F7F7F7Fu;  // bit 7 set where t != 4
-    return ((~ne3 | (~ne4 & (c << 7))) >> 7) & 0x01010101u;
+    const uint32_t d = t + 0x7D7D7D7Du;
+    const uint32_t e = d - (c + 0x01010101u);
+    return ((d & ~e) >> 7) & 0x01010101u;
 }
 
 // Sum of left, centre and right neighbours of the 16 cells c[0..3] of a lane

@@ -35,26 +35,50 @@ constexpr Ca2Shape kCa2Shapes[] = {
     {512, 512, 8, 16, 2},  {256, 256, 4, 16, 1},   {128, 128, 2, 8, 1},
 };
 
+// Pointwise shapes: (m, rho) -> threads, sub-blocks per tile.
+struct PointShape {
+    int m, rho, wg, sub;
+};
+constexpr PointShape kPointShapes[] = {
+    {2, 32, 256, 1}, {2, 16, 64, 1}, {2, 64, 256, 1}, {2, 128, 256, 2},
+    {3, 16, 256, 1}, {3, 8, 128, 1}, {3, 32, 256, 4},
+    {4, 8, 256, 1},  {4, 4, 64, 1},  {4, 16, 256, 16},
+};
+
+// CA3 shapes: (rho, threads) -> rows RY (y), planes RZ (z), rows per lane RL.
+struct Ca3Shape {
+    int rho, wg, ry, rz, rl, sub;
+};
+constexpr Ca3Shape kCa3Shapes[] = {
+    {128, 256, 64, 16, 2, 16}, {128, 128, 32, 16, 2, 32}, {128, 64, 32, 16, 4, 32},
+    {256, 256, 32, 16, 2, 128}, {64, 128, 64, 16, 2, 4},  {64, 64, 64, 16, 4, 4},
+    {32, 64, 32, 16, 1, 2},
+};
+
 // op class: 0 = pointwise (MAP/ACCUM/HITS/HASH), 1 = CA2, 2 = CA3
 int op_class(int op) { return op == OP_CA2 ? 1 : (op == OP_CA3 ? 2 : 0); }
 
 TileCfg default_tile(int m, int cls)
 {
     if (cls == 1) return {1024, 64, 64};
-    if (cls == 2) return {32, 256, 1};
-    if (m == 2) return {32, 256, 1};
-    if (m == 3) return {8, 256, 1};
-    return {4, 256, 1};
+    if (cls == 2) return {128, 256, 16};
+    for (const PointShape &c : kPointShapes)  // the first listed shape of an m is its default
+        if (c.m == m) return {c.rho, c.wg, c.sub};
+    return {0, 0, 1};
 }
 
 bool tile_supported(int m, int cls, int rho, int *wg, int *sub)
 {
     *sub = 1;
     if (cls == 0) {
-        *wg = 256;
-        if (m == 2) return rho == 16 || rho == 32 || rho == 64 || rho == 128;
-        if (m == 3) return rho == 8 || rho == 16;
-        return rho == 4 || rho == 8;
+        for (const PointShape &c : kPointShapes) {
+            if (c.m == m && c.rho == rho && (*wg == 0 || *wg == c.wg)) {
+                *wg = c.wg;
+                *sub = c.sub;
+                return true;
+            }
+        }
+        return false;
     }
     if (cls == 1) {  // the first listed shape of a rho is its default
         for (const Ca2Shape &c : kCa2Shapes) {
@@ -66,8 +90,15 @@ bool tile_supported(int m, int cls, int rho, int *wg, int *sub)
         }
         return false;
     }
-    *wg = 256;
-    return m == 3 && rho == 32;
+    if (m != 3) return false;
+    for (const Ca3Shape &c : kCa3Shapes) {
+        if (c.rho == rho && (*wg == 0 || *wg == c.wg)) {
+            *wg = c.wg;
+            *sub = c.sub;
+            return true;
+        }
+    }
+    return false;
 }
 
 std::mutex g_mu;
@@ -125,13 +156,23 @@ int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C
         cp.status = make_plan(m, n, beta, t.rho, bb, &cp.plan, &cp.counts);
         if (cp.status == kOk && !bb && (uint64_t)cp.plan.total * (uint64_t)t.sub > kMaxWorkgroups)
             cp.status = kErange;
-        if (cp.status == kOk && bb && m == 2 && (uint64_t)cp.plan.kbox * (uint64_t)t.sub > 65535)
-            cp.status = kErange;
+        if (cp.status == kOk && bb) {
+            const uint64_t kb = (uint64_t)cp.plan.kbox;
+            const uint64_t zext = (m == 2) ? (cls == 1 ? kb : 1) : (m == 3 ? kb : kb * kb);
+            if (zext * (uint64_t)t.sub > 65535) cp.status = kErange;
+        }
         if (cp.status == kOk) {
-            // largest offset inside one tile, in bytes (uint32 elements)
+            // The kernels use unsigned 32-bit offsets below a 64-bit base: the
+            // pointwise kernels inside one tile (element index), the automata
+            // inside one plane (CA3) or one sub-block of rows (CA2).
             __int128 span = 0;
-            for (int k = 0; k < m; ++k) span += (__int128)(t.rho + 1) * cp.plan.stride[k];
-            if (span * 4 >= ((__int128)1 << 31)) cp.status = kErange;
+            if (cls == 0) {
+                for (int k = 0; k < m; ++k) span += (__int128)(t.rho + 1) * cp.plan.stride[k];
+            } else {
+                span = (__int128)cp.plan.stride[m - 1] * (t.rho + 2) + 64;
+                if (cls == 2) span = (__int128)cp.plan.stride[2] + (__int128)cp.plan.stride[1] * 2 + 64;
+            }
+            if (span >= ((__int128)1 << 32)) cp.status = kErange;
         }
         if (g_plans.size() > 4096) g_plans.clear();
         it = g_plans.emplace(key, cp).first;
@@ -165,46 +206,44 @@ int check_buffers(int m, int64_t n, int op, const void *in, const void *out)
     return kOk;
 }
 
-template <int M, int RHO, int OP, bool BB>
+template <int M, int RHO, int NT, int SUB, int OP, bool BB>
 void launch_point(const Plan &P, dim3 grid, const void *in, void *out, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_point<M, RHO, OP, BB>), grid, dim3(256), 0, s, P,
+    hipLaunchKernelGGL((k_point<M, RHO, NT, OP, BB, SUB>), grid, dim3(NT), 0, s, P,
                        (const uint32_t *)in, (uint32_t *)out);
 }
 
-template <int M, int OP, bool BB>
-int dispatch_point_rho(int rho, const Plan &P, dim3 grid, const void *in, void *out, hipStream_t s)
+template <int OP, bool BB>
+int dispatch_point_shape(int m, int rho, const Plan &P, dim3 grid, const void *in, void *out,
+                         hipStream_t s)
 {
-    if constexpr (M == 2) {
-        switch (rho) {
-        case 16: launch_point<M, 16, OP, BB>(P, grid, in, out, s); return kOk;
-        case 32: launch_point<M, 32, OP, BB>(P, grid, in, out, s); return kOk;
-        case 64: launch_point<M, 64, OP, BB>(P, grid, in, out, s); return kOk;
-        case 128: launch_point<M, 128, OP, BB>(P, grid, in, out, s); return kOk;
-        }
-    } else if constexpr (M == 3) {
-        switch (rho) {
-        case 8: launch_point<M, 8, OP, BB>(P, grid, in, out, s); return kOk;
-        case 16: launch_point<M, 16, OP, BB>(P, grid, in, out, s); return kOk;
-        }
-    } else {
-        switch (rho) {
-        case 4: launch_point<M, 4, OP, BB>(P, grid, in, out, s); return kOk;
-        case 8: launch_point<M, 8, OP, BB>(P, grid, in, out, s); return kOk;
-        }
+    switch (m * 1000 + rho) {
+#define SMAP_PT(M, RHO, NT, SUB) \
+    case M * 1000 + RHO: launch_point<M, RHO, NT, SUB, OP, BB>(P, grid, in, out, s); return kOk;
+    SMAP_PT(2, 32, 256, 1)
+    SMAP_PT(2, 16, 64, 1)
+    SMAP_PT(2, 64, 256, 1)
+    SMAP_PT(2, 128, 256, 2)
+    SMAP_PT(3, 16, 256, 1)
+    SMAP_PT(3, 8, 128, 1)
+    SMAP_PT(3, 32, 256, 4)
+    SMAP_PT(4, 8, 256, 1)
+    SMAP_PT(4, 4, 64, 1)
+    SMAP_PT(4, 16, 256, 16)
+#undef SMAP_PT
     }
     return kEunsupported;
 }
 
-template <int M, bool BB>
-int dispatch_point(int op, int rho, const Plan &P, dim3 grid, const void *in, void *out,
+template <bool BB>
+int dispatch_point(int op, int m, int rho, const Plan &P, dim3 grid, const void *in, void *out,
                    hipStream_t s)
 {
     switch (op) {
-    case OP_MAP: return dispatch_point_rho<M, OP_MAP, BB>(rho, P, grid, in, out, s);
-    case OP_ACCUM: return dispatch_point_rho<M, OP_ACCUM, BB>(rho, P, grid, in, out, s);
-    case OP_HITS: return dispatch_point_rho<M, OP_HITS, BB>(rho, P, grid, in, out, s);
-    case OP_HASH: return dispatch_point_rho<M, OP_HASH, BB>(rho, P, grid, in, out, s);
+    case OP_MAP: return dispatch_point_shape<OP_MAP, BB>(m, rho, P, grid, in, out, s);
+    case OP_ACCUM: return dispatch_point_shape<OP_ACCUM, BB>(m, rho, P, grid, in, out, s);
+    case OP_HITS: return dispatch_point_shape<OP_HITS, BB>(m, rho, P, grid, in, out, s);
+    case OP_HASH: return dispatch_point_shape<OP_HASH, BB>(m, rho, P, grid, in, out, s);
     }
     return kEinval;
 }
@@ -217,9 +256,12 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P, const void *in, vo
     const uint32_t sub = (uint32_t)tc.sub;
     if (BB) {
         const uint32_t kb = (uint32_t)P.kbox;
-        grid = (m == 2) ? dim3(kb, kb * sub, 1) : (m == 3 ? dim3(kb, kb, kb) : dim3(kb, kb, kb * kb));
+        if (op == OP_CA2)
+            grid = dim3(kb, kb * sub, 1);
+        else
+            grid = (m == 2) ? dim3(kb, kb, sub) : (m == 3 ? dim3(kb, kb, kb * sub) : dim3(kb, kb, kb * kb * sub));
     } else {
-        grid = dim3(P.total * sub, 1, 1);
+        grid = (op == OP_CA3) ? dim3(P.total, sub, 1) : dim3(P.total * sub, 1, 1);
     }
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
@@ -244,14 +286,28 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P, const void *in, vo
         return kEunsupported;
     }
     if (op == OP_CA3) {
-        if (tc.rho != 32) return kEunsupported;
-        hipLaunchKernelGGL((k_ca3_32<BB>), grid, dim3(256), 0, s, P, (const uint8_t *)in,
-                           (uint8_t *)out);
-        return kOk;
+        const uint8_t *i8 = (const uint8_t *)in;
+        uint8_t *o8 = (uint8_t *)out;
+        switch (tc.rho * 10000 + tc.wg) {
+#define SMAP_CA3(RHO, WG, RY, RZ, RL)                                                             \
+        case RHO * 10000 + WG:                                                                    \
+            if (P.n < 15)                                                                         \
+                hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, true>), grid, dim3(WG), 0, s, P, i8, o8); \
+            else                                                                                  \
+                hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, false>), grid, dim3(WG), 0, s, P, i8, o8); \
+            return kOk;
+        SMAP_CA3(128, 256, 64, 16, 2)
+        SMAP_CA3(128, 128, 32, 16, 2)
+        SMAP_CA3(128, 64, 32, 16, 4)
+        SMAP_CA3(256, 256, 32, 16, 2)
+        SMAP_CA3(64, 128, 64, 16, 2)
+        SMAP_CA3(64, 64, 64, 16, 4)
+        SMAP_CA3(32, 64, 32, 16, 1)
+#undef SMAP_CA3
+        }
+        return kEunsupported;
     }
-    if (m == 2) return dispatch_point<2, BB>(op, tc.rho, P, grid, in, out, s);
-    if (m == 3) return dispatch_point<3, BB>(op, tc.rho, P, grid, in, out, s);
-    return dispatch_point<4, BB>(op, tc.rho, P, grid, in, out, s);
+    return dispatch_point<BB>(op, m, tc.rho, P, grid, in, out, s);
 }
 
 int do_launch(int m, int64_t n, int r, int beta, int op, const void *in, void *out,

@@ -1,19 +1,12 @@
 // smap_point.hpp -- per-element kernels MAP, ACCUM, HITS and HASH (uint32).
 //
-// One workgroup of 256 threads processes one tile of rho^m elements (the
-// test kernels of Section 5.1, Table tab:tests; HITS and HASH added).  Lanes
-// run along x_1, so a wave touches whole rho-element row segments.  The tile
-// comes from the H decode (one 1-D grid over the fused native + shell
-// pieces) or from the BB grid coordinates.  Only tiles that cross the
-// simplex boundary filter their elements (sum x <= n); tiles fully inside
-// skip the test, and BB tiles fully outside exit before touching memory.
+// The test kernels of Section 5.1, Table tab:tests, plus HITS and HASH.
+// The tile comes from the H decode (one 1-D grid over the fused native +
+// shell pieces) or from the BB grid coordinates; BB tiles fully outside the
+// simplex exit before touching memory.
 //
-// Element offsets inside a tile are separable: for the tile-local index
-// li = tid + 256 e (tid < 256) every coordinate bit-field of li is the sum
-// of its field in tid and its field in 256 e, so offset(li) = offset(tid) +
-// offset(256 e), the second term being a compile-time multiple of the
-// strides (scalar).  Per element the lane does one add and, in boundary
-// tiles only, one compare.
+// Rows of the box are unaligned for a general n (pitch n+1 elements); gfx9
+// global memory accepts unaligned 16-byte accesses.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,16 +50,34 @@ __device__ __forceinline__ bool wg_tile(const Plan &P, int32_t *t)
     return decode_h<M>(P, blockIdx.x, t);
 }
 
-template <int M, int RHO, int OP, bool BB>
-__global__ __launch_bounds__(256) void k_point(const Plan P, const uint32_t *in, uint32_t *out)
+// One tile (or one sub-block of a tile's rows) per NT-thread workgroup.  A
+// lane handles 4 consecutive elements of a row along x_1 (one 16-byte
+// access when all 4 lie in the simplex), G = rho/4 lanes cover a tile row,
+// and the workgroup steps through the tile's rows NT/G at a time.  Row
+// coordinates (x_2..x_m) are bit fields of the row index (rho is a power of
+// two).  A lane whose 4 elements are all inside uses the vector access; a
+// lane the hypotenuse cuts handles its elements one by one; lanes outside do
+// nothing.  SUB workgroups share a tile, each taking a contiguous range of
+// its rows.
+template <int M, int RHO, int NT, int OP, bool BB, int SUB>
+__global__ __launch_bounds__(NT) void k_point(const Plan P, const uint32_t *in, uint32_t *out)
 {
+    constexpr int G = RHO / 4;                   // lanes per tile row
     constexpr int LR = ilog2c(RHO);
-    constexpr int NE = ipowc(RHO, M);
-    constexpr int E = NE / 256;
-    static_assert(NE % 256 == 0, "tile must hold a multiple of 256 elements");
+    constexpr int ROWS = ipowc(RHO, M - 1);      // rows per tile
+    constexpr int RPI = NT / G;                  // rows per workgroup iteration
+    constexpr int RSUB = ROWS / SUB;             // rows per sub-block
+    static_assert(RHO >= 4 && NT % G == 0 && ROWS % SUB == 0 && RSUB % RPI == 0, "bad tile shape");
 
     int32_t t[4] = {0, 0, 0, 0};
-    if (!wg_tile<M, BB>(P, t)) return;
+    uint32_t sub;
+    if (BB) {
+        decode_bb(P, blockIdx.x, blockIdx.y, blockIdx.z / SUB, t);
+        sub = blockIdx.z % SUB;
+    } else {
+        if (!decode_h<M>(P, blockIdx.x / SUB, t)) return;
+        sub = blockIdx.x % SUB;
+    }
     int32_t x0[M];
     int32_t s0 = 0;
     int64_t base = 0;
@@ -78,48 +89,59 @@ __global__ __launch_bounds__(256) void k_point(const Plan P, const uint32_t *in,
     }
     const int32_t n = P.n;
     if (s0 > n) return;                               // BB tile outside the simplex
-    const bool full = s0 + M * (RHO - 1) <= n;
-
-    // per-thread part of the tile-local coordinates and offset
-    const uint32_t tid = threadIdx.x;
-    int32_t lt[M];
-    int32_t st = 0;
-    uint32_t ot = 0;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        lt[k] = (int32_t)((tid >> (k * LR)) & (RHO - 1));
-        st += lt[k];
-        ot += (uint32_t)lt[k] * (uint32_t)P.stride[k];
-    }
     const uint32_t *pin = in + base;
     uint32_t *pout = out + base;
 
+    const int cx = threadIdx.x % G;
+    const int32_t lx = 4 * cx;                       // tile-local x_1 of the lane's first element
+#pragma unroll 4
+    for (int it = 0; it < RSUB / RPI; ++it) {
+        const uint32_t ri = sub * RSUB + it * RPI + threadIdx.x / G;   // tile-local row index
+        int32_t rs = s0 + lx;                        // coordinate sum of the lane's first element
+        uint32_t off = (uint32_t)lx;                 // tile-local element offset
+        int32_t xr[M];
+        xr[0] = x0[0] + lx;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        // the per-iteration part: fields of 256 e (compile-time bit fields)
-        const uint32_t hi = (uint32_t)e * 256u;
-        int32_t le[M];
-        int32_t se = 0;
-        uint32_t oe = 0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            le[k] = (int32_t)((hi >> (k * LR)) & (RHO - 1));
-            se += le[k];
-            oe += (uint32_t)le[k] * (uint32_t)P.stride[k];
+        for (int k = 1; k < M; ++k) {
+            const int32_t l = (int32_t)((ri >> ((k - 1) * LR)) & (RHO - 1));
+            xr[k] = x0[k] + l;
+            rs += l;
+            off += (uint32_t)l * (uint32_t)P.stride[k];
         }
-        if (!full && s0 + st + se > n) continue;
-        const uint32_t off = ot + oe;
+        const int32_t v = n - rs + 1;                // elements of the lane inside the simplex
+        if (v <= 0) continue;
         if (OP == OP_MAP) {
-            asm volatile("" ::"v"(off));                 // keep the mapping, drop nothing
-        } else if (OP == OP_ACCUM) {
-            pout[off] = pin[off] + 1u;
+            asm volatile("" ::"v"(off), "v"(v));     // keep the mapping, drop nothing
         } else if (OP == OP_HITS) {
-            atomicAdd(pout + off, 1u);
-        } else if (OP == OP_HASH) {
-            int32_t x[M];
 #pragma unroll
-            for (int k = 0; k < M; ++k) x[k] = x0[k] + lt[k] + le[k];
-            pout[off] = hash32_words<M>(x);
+            for (int j = 0; j < 4; ++j)
+                if (j < v) atomicAdd(pout + off + j, 1u);
+        } else {
+            uint32_t r[4];
+            if (OP == OP_ACCUM) {
+                if (v >= 4) {
+                    const uint4 q = *reinterpret_cast<const uint4 *>(pin + off);
+                    r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) r[j] = j < v ? pin[off + j] : 0u;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) r[j] += 1u;
+            } else {  // OP_HASH
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    xr[0] = x0[0] + lx + j;
+                    r[j] = hash32_words<M>(xr);
+                }
+            }
+            if (v >= 4) {
+                *reinterpret_cast<uint4 *>(pout + off) = make_uint4(r[0], r[1], r[2], r[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (j < v) pout[off + j] = r[j];
+            }
         }
     }
 }

@@ -94,11 +94,17 @@ def test_set_tile_validation():
     with pytest.raises(smap.SimplexMapError):
         smap.set_tile(2, "accum", 24)
     with pytest.raises(smap.SimplexMapError):
+        smap.set_tile(4, "hash", 8, 64)
+    with pytest.raises(smap.SimplexMapError):
         smap.set_tile(2, "ca2", 256, wg_threads=512)
     with pytest.raises(smap.SimplexMapError):
         smap.set_tile(2, "ca2", 64)
     with pytest.raises(smap.SimplexMapError):
         smap.set_tile(3, "ca3", 16)
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_tile(3, "ca3", 32, 256)
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_tile(3, "ca3", 64, 256)
     smap.set_tile(2, "ca2", 128)
     assert smap.plan_info(2, 1000, "ca2")["rho"] == 128
     assert smap.plan_info(2, 1000, "ca2")["wg_threads"] == 128

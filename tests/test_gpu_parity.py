@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-POINT_TILES = {2: [16, 32, 64, 128], 3: [8, 16], 4: [4, 8]}
+POINT_TILES = {2: [16, 32, 64, 128], 3: [8, 16, 32], 4: [4, 8, 16]}
 CA2_TILES = [(1024, 64), (1024, 128), (1024, 256), (512, 512), (256, 256), (128, 128)]
 
 
@@ -165,16 +165,24 @@ def test_ca2_parity(smap):
 CA3_SIZES = list(range(0, 41)) + [62, 63, 64, 65, 66, 95, 96, 97, 127, 128, 150]
 
 
+CA3_TILES = [(128, 256), (128, 128), (128, 64), (256, 256), (64, 128), (64, 64), (32, 64)]
+
+
 def test_ca3_parity(smap):
-    for n in CA3_SIZES:
-        inp = si.box(3, n, "bern", 3000 + n, p=0.2 if n % 2 else 0.5)
-        want = to_dev(expected(3, n, "ca3", inp))
-        d_in = to_dev(inp)
-        for kind in ("h", "bb"):
-            say(f"ca3 n={n} {kind}")
-            d_out = fresh_out(3, n, "ca3")
-            launch(smap, kind, 3, n, "ca3", d_in, d_out)
-            assert same(d_out, want), (n, kind)
+    try:
+        for n in CA3_SIZES:
+            inp = si.box(3, n, "bern", 3000 + n, p=0.2 if n % 2 else 0.5)
+            want = to_dev(expected(3, n, "ca3", inp))
+            d_in = to_dev(inp)
+            for rho, wg in CA3_TILES:
+                smap.set_tile(3, "ca3", rho, wg)
+                for kind in ("h", "bb"):
+                    say(f"ca3 n={n} rho={rho} wg={wg} {kind}")
+                    d_out = fresh_out(3, n, "ca3")
+                    launch(smap, kind, 3, n, "ca3", d_in, d_out)
+                    assert same(d_out, want), (n, rho, wg, kind)
+    finally:
+        smap.set_tile(3, "ca3", 0)
 
 
 def test_ca2_two_steps_ping_pong(smap):

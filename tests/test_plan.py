@@ -22,10 +22,10 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 TILES = {  # (m, op) -> supported rho values
     (2, "hits"): [16, 32, 64, 128],
-    (3, "hits"): [8, 16],
-    (4, "hits"): [4, 8],
+    (3, "hits"): [8, 16, 32],
+    (4, "hits"): [4, 8, 16],
     (2, "ca2"): [128, 256, 512, 1024],
-    (3, "ca3"): [32],
+    (3, "ca3"): [32, 64, 128, 256],
 }
 
 
