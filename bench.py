@@ -27,31 +27,36 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
 # algorithmic HBM bytes per useful element (read + write)
 BYTES_PER_ELEMENT = {"accum": 8, "ca2": 2, "ca3": 2, "hash": 4, "hits": 8, "map": 0}
 
-# kernel sources whose change invalidates stored counter readings
-KERNEL_SOURCES = ["smap_decode.hpp", "smap_point.hpp", "smap_ca2.hpp", "smap_ca3.hpp"]
+# kernel sources whose change invalidates stored counter readings, per op
+KERNEL_SOURCES = {
+    "ca2": ["smap_decode.hpp", "smap_ca2.hpp"],
+    "ca3": ["smap_decode.hpp", "smap_ca2.hpp", "smap_ca3.hpp"],
+    "point": ["smap_decode.hpp", "smap_point.hpp"],
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_sha() -> str:
+def kernel_sha(op: str) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES.get(op, KERNEL_SOURCES["point"]):
         with open(os.path.join(ROOT, "paper_2208_11617_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload: str, per_launch_units: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when there is none or the kernel sources changed since it was taken."""
+def stored_traffic(workload: str, op: str):
+    """HBM bytes per launch of the H kernel from the committed rocprofv3
+    counter summary, or None when there is none or the kernel's sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_sha") != kernel_sha():
+    if rec.get("kernel_sha") != kernel_sha(op):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -69,6 +74,22 @@ def time_launches(fn, steps, warmup, stream):
     end.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(end) / steps  # ms per launch
+
+
+def copy_probe(nbytes, steps, stream):
+    """A plain streaming kernel over ``nbytes`` (torch's elementwise
+    bitwise_not on uint8: one read and one write per byte, like a copy, but
+    always a kernel rather than a DMA transfer): the achievable read+write
+    rate on this GPU, and the known-size kernel that calibrates the HBM byte
+    counters."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    ms = time_launches(lambda i: torch.bitwise_not(src, out=dst), steps, 3, stream)
+    del src, dst
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms,
+            "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
 def cpu_baseline(w, budget_s=12.0):
@@ -118,12 +139,13 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-bb", action="store_true", help="skip timing the BB baseline")
+    ap.add_argument("--no-copy", action="store_true", help="skip the plain-copy probe")
     ap.add_argument("--beta", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -165,11 +187,16 @@ def main():
         log("timing BB")
         bb_ms = time_launches(step_fn(smap.bb_launch), args.steps, args.warmup, stream)
 
+    copy = None
+    if not args.no_copy:
+        log("timing a plain copy of the same byte count")
+        copy = copy_probe(max(useful * BYTES_PER_ELEMENT[op] // 2, 1 << 20), 20, stream)
+
     info_h = smap.plan_info(m, n, op, beta=args.beta)
     info_bb = smap.plan_info(m, n, op, use_bb=True)
     alg_bytes = useful * BYTES_PER_ELEMENT[op]
     achieved = alg_bytes / (h_ms * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload, useful)
+    traffic = stored_traffic(args.workload, op)
     value = useful / (h_ms * 1e-3)
 
     res = {
@@ -204,8 +231,12 @@ def main():
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
             "kernel": f"{op} H launch",
+            "kernel_sha": kernel_sha(op),
             "bytes_per_launch": alg_bytes,
+            "copy_gbs": None if copy is None else copy["gbs"],
+            "frac_of_copy": None if copy is None else achieved / copy["gbs"],
         },
+        "copy": copy,
         "cpu_baseline": None,
     }
     if not args.no_cpu:

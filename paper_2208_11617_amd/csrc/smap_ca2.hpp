@@ -139,11 +139,13 @@ __global__ __launch_bounds__(64 * W) void k_ca2(const Plan P, const uint8_t *__r
     int32_t t[4] = {0, 0, 0, 0};
     uint32_t sub;
     if (BB) {
-        decode_bb(P, blockIdx.x, blockIdx.y / SUB, 0, t);
-        sub = blockIdx.y % SUB;
+        const WgId g = wg_id(P);
+        decode_bb(P, g.x, g.y / SUB, 0, t);
+        sub = g.y % SUB;
     } else {
-        if (!decode_h<2>(P, blockIdx.x / SUB, t)) return;
-        sub = blockIdx.x % SUB;
+        const WgId g = wg_id(P);
+        if (!decode_h<2>(P, g.x / SUB, t)) return;
+        sub = g.x % SUB;
     }
     const int32_t n = P.n;
     const int32_t x0 = t[0] * RHO, y0 = t[1] * RHO + (int32_t)sub * (W * SEGS * R);
@@ -176,7 +178,6 @@ __global__ __launch_bounds__(64 * W) void k_ca2(const Plan P, const uint8_t *__r
     // end of the buffer (worst case y = n, x = 0: n (n+1) + 16 <= (n+1)^2),
     // and neither does the 4-byte halo access; the host launches the SAFE
     // instantiation (byte-safe loads through ld_masked) for smaller n.
-    constexpr bool safe = SAFE;
 
     // Raw loads of wave row r: the lane's 16 cells (if any is in the
     // simplex) and its halo dword (first/last lane of a segment).  No masking

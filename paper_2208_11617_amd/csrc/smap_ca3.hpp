@@ -57,11 +57,18 @@ __global__ __launch_bounds__((RHO / 16) * (RY / RL)) void k_ca3(const Plan P, co
     int32_t t[4] = {0, 0, 0, 0};
     uint32_t sub;
     if (BB) {
-        decode_bb(P, blockIdx.x, blockIdx.y, blockIdx.z / SUB, t);
-        sub = blockIdx.z % SUB;
+        const WgId g = wg_id(P);
+        decode_bb(P, g.x, g.y, g.z / SUB, t);
+        sub = g.z % SUB;
     } else {  // grid (map grid, SUB): x-adjacent tiles of one sub-block run together
-        if (!decode_h<3>(P, blockIdx.x, t)) return;
-        sub = blockIdx.y;
+        const WgId g = wg_id(P);
+#ifdef SMAP_CA3_TILE_MAJOR
+        if (!decode_h<3>(P, g.x / SUB, t)) return;
+        sub = g.x % SUB;
+#else
+        if (!decode_h<3>(P, g.x, t)) return;
+        sub = g.y;
+#endif
     }
     const int32_t n = P.n;
     const int32_t x0 = t[0] * RHO;

@@ -84,7 +84,43 @@ struct Plan {
     uint32_t base_count[4];      // workgroups of the base map of each piece
     uint32_t lvl_start[kMaxLevels + 1];
     int64_t stride[4];           // element strides (n+1)^k
+    uint32_t grid[3];            // launch grid of this launch (set per launch)
+    uint32_t nwg;                // grid[0] * grid[1] * grid[2] (< 2^32)
+    uint32_t remap;              // 1: renumber workgroups with xcd_remap
 };
+
+// Launch order.  The 8 XCDs of the chip each have their own L2; workgroup L
+// (x fastest, then y, then z) is dispatched to XCD L mod 8.  Renumbering
+// L -> xcd_remap(L) gives each XCD one contiguous range of logical ids, so
+// neighbouring tiles (which share cache lines at their row ends and halo
+// rows) run on the same XCD at about the same time.  A bijection of
+// [0, nwg): XCD x holds the cnt(x) = nwg/8 + (x < nwg mod 8) ids starting at
+// x * (nwg/8) + min(x, nwg mod 8).
+SMAP_HD uint32_t xcd_remap(uint32_t L, uint32_t nwg)
+{
+    const uint32_t per = nwg >> 3, rem = nwg & 7u;
+    const uint32_t x = L & 7u;
+    return x * per + (x < rem ? x : rem) + (L >> 3);
+}
+
+#if defined(__HIPCC__)
+// Logical workgroup coordinates of this workgroup in the launch grid.
+struct WgId {
+    uint32_t x, y, z;
+};
+__device__ __forceinline__ WgId wg_id(const Plan &P)
+{
+#ifndef SMAP_NO_XCD_REMAP
+    if (P.remap) {
+        const uint32_t L = (blockIdx.z * P.grid[1] + blockIdx.y) * P.grid[0] + blockIdx.x;
+        const uint32_t g = xcd_remap(L, P.nwg);
+        const uint32_t gx = g % P.grid[0], r = g / P.grid[0];
+        return {gx, r % P.grid[1], r / P.grid[1]};
+    }
+#endif
+    return {blockIdx.x, blockIdx.y, blockIdx.z};
+}
+#endif
 
 SMAP_HD uint32_t ilog2u(uint32_t v)  // floor(log2 v), v > 0: 31 - clz(v)
 {

@@ -160,6 +160,8 @@ int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C
             const uint64_t kb = (uint64_t)cp.plan.kbox;
             const uint64_t zext = (m == 2) ? (cls == 1 ? kb : 1) : (m == 3 ? kb : kb * kb);
             if (zext * (uint64_t)t.sub > 65535) cp.status = kErange;
+            // workgroups are renumbered with 32-bit linear ids
+            if ((uint64_t)cp.plan.total * (uint64_t)t.sub > UINT32_MAX) cp.status = kErange;
         }
         if (cp.status == kOk) {
             // The kernels use unsigned 32-bit offsets below a 64-bit base: the
@@ -249,10 +251,11 @@ int dispatch_point(int op, int m, int rho, const Plan &P, dim3 grid, const void 
 }
 
 template <bool BB>
-int dispatch(int m, int op, const TileCfg &tc, const Plan &P, const void *in, void *out,
+int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, void *out,
              hipStream_t s)
 {
     dim3 grid;
+    const Plan &P = P0;  // grid and plan checks
     const uint32_t sub = (uint32_t)tc.sub;
     if (BB) {
         const uint32_t kb = (uint32_t)P.kbox;
@@ -261,8 +264,24 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P, const void *in, vo
         else
             grid = (m == 2) ? dim3(kb, kb, sub) : (m == 3 ? dim3(kb, kb, kb * sub) : dim3(kb, kb, kb * kb * sub));
     } else {
+#ifdef SMAP_CA3_TILE_MAJOR
+        grid = dim3(P.total * sub, 1, 1);
+#else
         grid = (op == OP_CA3) ? dim3(P.total, sub, 1) : dim3(P.total * sub, 1, 1);
+#endif
     }
+    Plan PL = P0;  // the kernels renumber workgroups over this grid
+    PL.grid[0] = grid.x;
+    PL.grid[1] = grid.y;
+    PL.grid[2] = grid.z;
+    PL.nwg = grid.x * grid.y * grid.z;
+    // H runs XCD-contiguous (its workgroups are nearly all useful, so every
+    // XCD gets an equal share of the work).  BB keeps the hardware order: a
+    // contiguous split would hand the XCDs at the end of the range mostly
+    // empty box tiles.  The 3-D automaton also keeps the hardware order
+    // (measured faster: its sub-major order already spreads the concurrent
+    // workgroups over the buffer).
+    PL.remap = (BB || op == OP_CA3) ? 0u : 1u;
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
         uint8_t *o8 = (uint8_t *)out;
@@ -271,9 +290,9 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P, const void *in, vo
 #define SMAP_CA2(RHO, WG, W, R)                                                                  \
         case RHO * 10000 + WG:                                                                    \
             if (P.n < 15)                                                                         \
-                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, true>), grid, dim3(WG), 0, s, P, i8, o8); \
+                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, true>), grid, dim3(WG), 0, s, PL, i8, o8); \
             else                                                                                  \
-                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, false>), grid, dim3(WG), 0, s, P, i8, o8); \
+                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, false>), grid, dim3(WG), 0, s, PL, i8, o8); \
             return kOk;
         SMAP_CA2(1024, 64, 1, 16)
         SMAP_CA2(1024, 128, 2, 16)
@@ -292,9 +311,9 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P, const void *in, vo
 #define SMAP_CA3(RHO, WG, RY, RZ, RL)                                                             \
         case RHO * 10000 + WG:                                                                    \
             if (P.n < 15)                                                                         \
-                hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, true>), grid, dim3(WG), 0, s, P, i8, o8); \
+                hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, true>), grid, dim3(WG), 0, s, PL, i8, o8); \
             else                                                                                  \
-                hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, false>), grid, dim3(WG), 0, s, P, i8, o8); \
+                hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, false>), grid, dim3(WG), 0, s, PL, i8, o8); \
             return kOk;
         SMAP_CA3(128, 256, 64, 16, 2)
         SMAP_CA3(128, 128, 32, 16, 2)
@@ -307,7 +326,7 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P, const void *in, vo
         }
         return kEunsupported;
     }
-    return dispatch_point<BB>(op, m, tc.rho, P, grid, in, out, s);
+    return dispatch_point<BB>(op, m, tc.rho, PL, grid, in, out, s);
 }
 
 int do_launch(int m, int64_t n, int r, int beta, int op, const void *in, void *out,

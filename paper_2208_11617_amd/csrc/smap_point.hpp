@@ -39,17 +39,6 @@ __device__ __forceinline__ uint32_t hash32_words(const int32_t *x)
     return h;
 }
 
-// Tile coordinates of this workgroup, or false if it has none.
-template <int M, bool BB>
-__device__ __forceinline__ bool wg_tile(const Plan &P, int32_t *t)
-{
-    if (BB) {
-        decode_bb(P, blockIdx.x, blockIdx.y, blockIdx.z, t);
-        return true;
-    }
-    return decode_h<M>(P, blockIdx.x, t);
-}
-
 // One tile (or one sub-block of a tile's rows) per NT-thread workgroup.  A
 // lane handles 4 consecutive elements of a row along x_1 (one 16-byte
 // access when all 4 lie in the simplex), G = rho/4 lanes cover a tile row,
@@ -72,11 +61,13 @@ __global__ __launch_bounds__(NT) void k_point(const Plan P, const uint32_t *in, 
     int32_t t[4] = {0, 0, 0, 0};
     uint32_t sub;
     if (BB) {
-        decode_bb(P, blockIdx.x, blockIdx.y, blockIdx.z / SUB, t);
-        sub = blockIdx.z % SUB;
+        const WgId g = wg_id(P);
+        decode_bb(P, g.x, g.y, g.z / SUB, t);
+        sub = g.z % SUB;
     } else {
-        if (!decode_h<M>(P, blockIdx.x / SUB, t)) return;
-        sub = blockIdx.x % SUB;
+        const WgId g = wg_id(P);
+        if (!decode_h<M>(P, g.x / SUB, t)) return;
+        sub = g.x % SUB;
     }
     int32_t x0[M];
     int32_t s0 = 0;
