@@ -165,6 +165,106 @@ int simplex_set_tile(int m, int op, int rho, int wg_threads);
 /* Static, human-readable text for a status code. */
 const char *simplex_strerror(int status);
 
+/* ---- batched launch ---------------------------------------------------
+ *
+ * One job of a batched launch: one automaton step over Delta_n^m with the
+ * job's own buffers (layout and rules as for simplex_map_launch).
+ *   m = 2 with op SMAP_OP_CA2, or m = 3 with op SMAP_OP_CA3; n >= 0.
+ *   buf_in, buf_out: device pointers to (n+1)^m uint8 cells, not
+ *   overlapping each other.  Different jobs may share an input buffer but
+ *   no job's output may overlap any buffer of another job in the batch.
+ */
+struct simplex_job {
+    int32_t m;
+    int32_t op;
+    int64_t n;
+    const void *buf_in;
+    void *buf_out;
+};
+
+/*
+ * Steps every job of `jobs[0..njobs)` with the H map in as few launches as
+ * possible: the H-mapped tile ranges of all jobs of one op class are
+ * concatenated into one grid, and a device-side table of the jobs'
+ * workgroup prefix sums tells each workgroup which job and which tile it
+ * takes (a binary search, wave-uniform), then decodes its tile with the
+ * job's own H plan (default r and beta).  A step's result does not depend
+ * on the map or the tiles, so every job's output equals what
+ * simplex_map_launch gives for it alone.  Batched tiles: rho = 256 for CA2
+ * (256 threads, one workgroup per tile), rho = 64 for CA3 (128 threads).
+ *
+ * The table travels from pinned host memory to device memory with an
+ * asynchronous copy on `stream`, then the launch follows on `stream`; the
+ * call returns without synchronising.  The library keeps a small ring of
+ * table buffers per device (allocated on the first call, kept until the
+ * process ends) and waits, on the host, only when a ring slot is still in
+ * use by an earlier batch.  Jobs of one class are launched together up to
+ * 4096 per launch (more are split over several launches).
+ *
+ * Errors: SMAP_EINVAL for njobs < 0, a NULL `jobs` with njobs > 0, a job
+ * with an unsupported (m, op), a negative n, NULL or overlapping buffers;
+ * SMAP_ERANGE for sizes beyond the index range; SMAP_EHIP if an allocation,
+ * copy or launch fails.  All jobs are checked before anything is enqueued.
+ * njobs == 0 is a no-op.
+ */
+int simplex_batch_launch(const struct simplex_job *jobs, int32_t njobs, void *stream);
+
+/* ---- serving loop -------------------------------------------------------
+ *
+ * A request stream of automaton-step jobs (the continuous-batching serving
+ * loop).  Each job's input is already resident on the device; its output
+ * is placed in a device arena whose size is the memory budget.
+ */
+struct simplex_serve_job {
+    int32_t m;            /* 2 (op SMAP_OP_CA2) or 3 (op SMAP_OP_CA3) */
+    int32_t op;
+    int64_t n;
+    const void *buf_in;   /* device, (n+1)^m uint8 cells */
+    double arrival_s;     /* arrival time, seconds after the start of the run;
+                             non-decreasing over the job array */
+};
+
+/* What happened to one job (times in seconds after the start of the run,
+ * measured with device events for the completion). */
+struct simplex_serve_record {
+    double admit_s;       /* output memory granted */
+    double launch_s;      /* its launch enqueued */
+    double done_s;        /* its launch finished on the device */
+    uint64_t out_offset;  /* byte offset of its output in the arena */
+    int32_t batch;        /* index of the launch group that ran it */
+    int32_t status;       /* SMAP_OK, or the error of its launch */
+};
+
+#define SMAP_SERVE_SEQUENTIAL 0  /* one simplex_map_launch per job, in arrival order */
+#define SMAP_SERVE_BATCHED 1     /* continuous batching with simplex_batch_launch */
+
+/*
+ * Replays `jobs` in real time on the current device and returns when every
+ * job has completed.  The inputs must be ready before the call (the loop
+ * runs on streams of its own: synchronise the device after producing them).  Admission is by memory: a job is admitted, in arrival
+ * order, once its (n+1)^m output bytes (rounded up to 256) fit in the
+ * arena [arena, arena + arena_bytes); its memory returns to the arena when
+ * its launch has completed, unless keep_outputs is non-zero (then every
+ * output stays where it was written, and the arena must hold all of them).
+ *
+ * SMAP_SERVE_SEQUENTIAL: each admitted job is launched alone with the H map
+ * as soon as it is admitted, all on one stream.
+ * SMAP_SERVE_BATCHED: admitted jobs wait for a launch slot; whenever fewer
+ * than `max_inflight` batches are running, all admitted, not yet launched
+ * jobs go out as one simplex_batch_launch.  Batches alternate between two
+ * streams of the default priority (created and destroyed by the call), so
+ * consecutive batches overlap on the device.  Jobs that arrive while
+ * others run join the next batch.
+ *
+ * records (may be NULL) receives one entry per job.  Errors: SMAP_EINVAL for
+ * bad arguments (including a job that could never fit the arena),
+ * SMAP_EHIP for a runtime failure; the run stops at the first error after
+ * waiting for the work already enqueued.
+ */
+int simplex_serve_run(const struct simplex_serve_job *jobs, int32_t njobs, void *arena,
+                      uint64_t arena_bytes, int32_t mode, int32_t max_inflight,
+                      int32_t keep_outputs, struct simplex_serve_record *records);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,9 @@ OPS = {"map": OP_MAP, "accum": OP_ACCUM, "hits": OP_HITS, "hash": OP_HASH,
 # names declared in include/simplexmap.h
 EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_plan_info", "simplex_plan_tiles", "simplex_set_tile",
-           "simplex_strerror")
+           "simplex_strerror", "simplex_batch_launch", "simplex_serve_run")
+
+SERVE_SEQUENTIAL, SERVE_BATCHED = 0, 1
 
 
 class SimplexMapError(RuntimeError):
@@ -56,6 +58,25 @@ class PlanInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Job(ctypes.Structure):
+    """struct simplex_job"""
+    _fields_ = [("m", ctypes.c_int32), ("op", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("buf_in", ctypes.c_void_p), ("buf_out", ctypes.c_void_p)]
+
+
+class ServeJob(ctypes.Structure):
+    """struct simplex_serve_job"""
+    _fields_ = [("m", ctypes.c_int32), ("op", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("buf_in", ctypes.c_void_p), ("arrival_s", ctypes.c_double)]
+
+
+class ServeRecord(ctypes.Structure):
+    """struct simplex_serve_record"""
+    _fields_ = [("admit_s", ctypes.c_double), ("launch_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("out_offset", ctypes.c_uint64),
+                ("batch", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -82,6 +103,11 @@ def lib():
     L.simplex_plan_tiles.restype = ci
     L.simplex_set_tile.argtypes = [ci, ci, ci, ci]
     L.simplex_set_tile.restype = ci
+    L.simplex_batch_launch.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, vp]
+    L.simplex_batch_launch.restype = ci
+    L.simplex_serve_run.argtypes = [ctypes.POINTER(ServeJob), ctypes.c_int32, vp, u64, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ServeRecord)]
+    L.simplex_serve_run.restype = ci
     L.simplex_strerror.argtypes = [ci]
     L.simplex_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -163,3 +189,46 @@ def plan_tiles(m, n, op, use_bb=False, r=0, beta=0):
 
 def set_tile(m, op, rho, wg_threads=0) -> None:
     _check(lib().simplex_set_tile(m, _op(op), rho, wg_threads), "simplex_set_tile")
+
+
+def _job_array(jobs):
+    """jobs: iterable of (m, op, n, buf_in, buf_out) with tensors or raw pointers."""
+    def p(x):
+        return None if x is None else (x if isinstance(x, int) else x.data_ptr())
+    arr = (Job * max(len(jobs), 1))()
+    for i, (m, op, n, a, b) in enumerate(jobs):
+        arr[i] = Job(m, _op(op), n, p(a), p(b))
+    return arr
+
+
+def batch_launch_raw(jobs, njobs=None, stream_ptr=None) -> int:
+    """Status-returning batched launch (jobs as for batch_launch)."""
+    arr = _job_array(jobs)
+    return lib().simplex_batch_launch(arr, len(jobs) if njobs is None else njobs, stream_ptr)
+
+
+def batch_launch(jobs, stream=None) -> None:
+    """One step of every (m, op, n, buf_in, buf_out) job, batched by class."""
+    arr = _job_array(jobs)
+    _check(lib().simplex_batch_launch(arr, len(jobs), _stream(stream)), "simplex_batch_launch")
+
+
+def serve_run_raw(jobs, arena_ptr, arena_bytes, mode, max_inflight=2, keep_outputs=False):
+    """jobs: list of (m, op, n, buf_in, arrival_s).  Returns (status, records)."""
+    def p(x):
+        return x if isinstance(x, int) else x.data_ptr()
+    arr = (ServeJob * max(len(jobs), 1))()
+    for i, (m, op, n, a, t) in enumerate(jobs):
+        arr[i] = ServeJob(m, _op(op), n, p(a), float(t))
+    recs = (ServeRecord * max(len(jobs), 1))()
+    rc = lib().simplex_serve_run(arr, len(jobs), arena_ptr, arena_bytes, mode, max_inflight,
+                                 1 if keep_outputs else 0, recs)
+    return rc, [dict((f, getattr(recs[i], f)) for f, _ in ServeRecord._fields_)
+                for i in range(len(jobs))]
+
+
+def serve_run(jobs, arena, mode, max_inflight=2, keep_outputs=False):
+    """Replay a job stream (see simplex_serve_run); `arena` is a uint8 device tensor."""
+    rc, recs = serve_run_raw(jobs, arena.data_ptr(), arena.numel(), mode, max_inflight, keep_outputs)
+    _check(rc, "simplex_serve_run")
+    return recs

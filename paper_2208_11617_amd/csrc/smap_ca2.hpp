@@ -121,32 +121,28 @@ __device__ __forceinline__ uint32_t lane_next(const uint32_t *c, uint32_t e, int
     return sl == S - 1 ? e : d;
 }
 
-// One Life step of a rho x rho tile.  Each lane holds 16 cells of a row
-// (one unaligned 16-byte access, four SWAR dwords); a segment of rho/16
-// lanes covers a tile row; each segment walks R rows.  A tile is split into
-// SUB = rho / (W * SEGS * R) sub-blocks of rows, one workgroup each (the
-// launch grid is the map's grid times SUB, sub-blocks of a tile adjacent).
-template <int RHO, int W, int R, int D, bool BB, bool SAFE>
-__global__ __launch_bounds__(64 * W) void k_ca2(const Plan P, const uint8_t *__restrict__ in,
-                                                uint8_t *__restrict__ out)
-{
-    constexpr int S = RHO / 16;          // lanes per tile row
-    constexpr int SEGS = 64 / S;         // row segments per wave
-    constexpr int SUB = RHO / (W * SEGS * R);
+// Shape constants of a CA2 tile walk: S lanes per tile row, SEGS row
+// segments per wave, SUB sub-blocks (workgroups) per tile.
+template <int RHO, int W, int R>
+struct Ca2Walk {
+    static constexpr int S = RHO / 16;
+    static constexpr int SEGS = 64 / S;
+    static constexpr int SUB = RHO / (W * SEGS * R);
     static_assert(S >= 2 && S <= 64 && 64 % S == 0 && R >= 1 && SUB >= 1 &&
                   SUB * W * SEGS * R == RHO && (SUB & (SUB - 1)) == 0, "bad CA2 tile shape");
+};
 
-    int32_t t[4] = {0, 0, 0, 0};
-    uint32_t sub;
-    if (BB) {
-        const WgId g = wg_id(P);
-        decode_bb(P, g.x, g.y / SUB, 0, t);
-        sub = g.y % SUB;
-    } else {
-        const WgId g = wg_id(P);
-        if (!decode_h<2>(P, g.x / SUB, t)) return;
-        sub = g.x % SUB;
-    }
+// One Life step of sub-block `sub` of the rho x rho tile t (workgroup body).
+// Each lane holds 16 cells of a row (one unaligned 16-byte access, four SWAR
+// dwords); a segment of rho/16 lanes covers a tile row; each segment walks R
+// rows.  A tile is split into SUB = rho / (W * SEGS * R) sub-blocks of rows,
+// one workgroup each.
+template <int RHO, int W, int R, int D, bool SAFE>
+__device__ __forceinline__ void ca2_tile(const Plan &P, const uint8_t *__restrict__ in,
+                                         uint8_t *__restrict__ out, const int32_t *t, uint32_t sub)
+{
+    constexpr int S = Ca2Walk<RHO, W, R>::S;
+    constexpr int SEGS = Ca2Walk<RHO, W, R>::SEGS;
     const int32_t n = P.n;
     const int32_t x0 = t[0] * RHO, y0 = t[1] * RHO + (int32_t)sub * (W * SEGS * R);
     if (x0 + y0 > n) return;
@@ -286,6 +282,26 @@ __global__ __launch_bounds__(64 * W) void k_ca2(const Plan P, const uint8_t *__r
             }
         }
     }
+}
+
+// The CA2 kernel: the launch grid is the map's grid times SUB (sub-blocks of
+// a tile adjacent in H, the y grid coordinate in BB).
+template <int RHO, int W, int R, int D, bool BB, bool SAFE>
+__global__ __launch_bounds__(64 * W) void k_ca2(const Plan P, const uint8_t *__restrict__ in,
+                                                uint8_t *__restrict__ out)
+{
+    constexpr int SUB = Ca2Walk<RHO, W, R>::SUB;
+    int32_t t[4] = {0, 0, 0, 0};
+    uint32_t sub;
+    const WgId g = wg_id(P);
+    if (BB) {
+        decode_bb(P, g.x, g.y / SUB, 0, t);
+        sub = g.y % SUB;
+    } else {
+        if (!decode_h<2>(P, g.x / SUB, t)) return;
+        sub = g.x % SUB;
+    }
+    ca2_tile<RHO, W, R, D, SAFE>(P, in, out, t, sub);
 }
 
 }  // namespace smap

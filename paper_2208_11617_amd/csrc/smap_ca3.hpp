@@ -7,22 +7,29 @@
 // Work split.  The map (H or BB) gives a rho^3 tile; the tile is split into
 // sub-blocks of rho (x) x RY (y) x RZ (z) cells, one workgroup each.  The
 // launch orders the sub-block index slowest, so workgroups that run together
-// cover neighbouring tiles of the same sub-block position.  A lane owns 16
-// consecutive cells of RL consecutive rows (x .. x+15 at y .. y+RL-1, fixed
-// z); a group of rho/16 lanes covers RL tile rows.  The workgroup walks its
-// RZ planes along z.  For each input plane a lane reads the rows y-1 ..
-// y+RL straight from global memory (16-byte accesses; the outer two rows
-// are other lanes' rows, so those re-reads are served by the caches), takes
-// the left/right neighbour bytes from the adjacent lanes by DPP (halo bytes
-// by one extra load at the row-group edges), and forms the in-plane 3x3 box
-// sum S(z) of each of its rows (<= 9 per byte).  The 3x3x3 sum including
-// the centre is S(z-1)+S(z)+S(z+1) (<= 27); the sums of the two previous
-// planes stay in registers as the walk proceeds.
-
-// Boundary handling is per lane, as in the 2-D kernel: inside lanes use
-// plain 16-byte accesses, the lane the hypotenuse cuts masks its bytes,
-// lanes outside touch nothing; the SAFE instantiation (n < 15) reads byte by
-// byte near the end of the buffer.
+// cover neighbouring tiles of the same sub-block position.  The workgroup
+// walks its RZ planes along z.  Each plane of its slab, with one halo row on
+// each side in y and four halo bytes on each side in x, is staged in LDS:
+// the (RY+2) rows of x0-4 .. x0+rho+4 are cut into 16-byte chunks that the
+// lanes load from global memory (unaligned 16-byte accesses), clear outside
+// the simplex, and write to LDS.  Every staged byte is read from global
+// memory once per workgroup, and the zeroed cells outside the simplex make
+// the neighbour sums need no boundary test.  Two LDS buffers alternate, with
+// one barrier per plane; the chunk loads of the next two planes are in
+// flight while a plane is summed.
+//
+// A lane owns 16 consecutive cells of RL consecutive rows (x .. x+15 at
+// y .. y+RL-1); rho/16 lanes cover RL tile rows.  From LDS it reads, for each
+// of its RL+2 rows, 24 bytes: the dword left of its cells, the 16 cells and
+// the dword right of them, and forms the in-plane 3x3 box sums S(z) of its
+// RL rows (<= 9 per byte).  The 3x3x3 sum including the centre is
+// S(z-1)+S(z)+S(z+1) (<= 27); the sums of the two previous planes stay in
+// registers as the walk proceeds.
+//
+// Stores go straight from registers: a 16-byte store when the lane's cells
+// are all inside, the cells inside one by one on the lane the hypotenuse
+// cuts, nothing outside.  The SAFE instantiation (n < 15) loads byte by byte
+// near the end of the buffer.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,32 +51,31 @@ __device__ __forceinline__ uint32_t rule_b6s567(uint32_t t, uint32_t c)
     return ((d & ~e) >> 7) & 0x01010101u;
 }
 
-template <int RHO, int RY, int RZ, int RL, bool BB, bool SAFE>
-__global__ __launch_bounds__((RHO / 16) * (RY / RL)) void k_ca3(const Plan P, const uint8_t *__restrict__ in,
-                                                                uint8_t *__restrict__ out)
-{
-    constexpr int G = RHO / 16;            // lanes per tile row
-    constexpr int NR = RL + 2;             // rows read per plane by a lane
-    constexpr int SUBY = RHO / RY, SUBZ = RHO / RZ, SUB = SUBY * SUBZ;
-    static_assert(G >= 2 && 64 % G == 0 && (G * (RY / RL)) % 64 == 0 && RY % RL == 0 &&
-                  RHO % RY == 0 && RHO % RZ == 0, "bad CA3 tile shape");
+// Shape constants of a CA3 tile walk.
+template <int RHO, int RY, int RZ, int RL>
+struct Ca3Walk {
+    static constexpr int G = RHO / 16;                 // lanes per tile row
+    static constexpr int NT = G * (RY / RL);           // threads
+    static constexpr int SUBY = RHO / RY, SUBZ = RHO / RZ, SUB = SUBY * SUBZ;
+    static_assert(G >= 2 && 64 % G == 0 && NT % 64 == 0 && RY % RL == 0 && RHO % RY == 0 &&
+                  RHO % RZ == 0, "bad CA3 tile shape");
+};
 
-    int32_t t[4] = {0, 0, 0, 0};
-    uint32_t sub;
-    if (BB) {
-        const WgId g = wg_id(P);
-        decode_bb(P, g.x, g.y, g.z / SUB, t);
-        sub = g.z % SUB;
-    } else {  // grid (map grid, SUB): x-adjacent tiles of one sub-block run together
-        const WgId g = wg_id(P);
-#ifdef SMAP_CA3_TILE_MAJOR
-        if (!decode_h<3>(P, g.x / SUB, t)) return;
-        sub = g.x % SUB;
-#else
-        if (!decode_h<3>(P, g.x, t)) return;
-        sub = g.y;
-#endif
-    }
+// One B6/S567 step of sub-block `sub` of the rho^3 tile t (workgroup body;
+// every thread of the workgroup must call it: it has barriers).
+template <int RHO, int RY, int RZ, int RL, bool SAFE>
+__device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restrict__ in,
+                                         uint8_t *__restrict__ out, const int32_t *t, uint32_t sub)
+{
+    using Sh = Ca3Walk<RHO, RY, RZ, RL>;
+    constexpr int G = Sh::G, NT = Sh::NT, SUBY = Sh::SUBY;
+    constexpr int C = (RHO + 8 + 15) / 16;      // 16-byte chunks per staged row (x0-4 .. x0+rho+4)
+    constexpr int PITCH = 16 * C;               // LDS bytes per staged row
+    constexpr int ROWS = RY + 2;                // staged rows y0-1 .. y0+RY
+    constexpr int NCH = ROWS * C;               // chunks per staged plane
+    constexpr int KQ = (NCH + NT - 1) / NT;     // chunks per lane per plane
+    __shared__ __align__(16) uint8_t lds[2][ROWS * PITCH];
+
     const int32_t n = P.n;
     const int32_t x0 = t[0] * RHO;
     const int32_t y0 = t[1] * RHO + (int32_t)(sub % SUBY) * RY;
@@ -77,123 +83,180 @@ __global__ __launch_bounds__((RHO / 16) * (RY / RL)) void k_ca3(const Plan P, co
     if (x0 + y0 + z0 > n) return;                 // uniform: no cell in this sub-block
     // output planes with a simplex cell: z0 .. z0 + nz - 1 (workgroup-uniform)
     const int32_t nz = min(RZ, n - x0 - y0 - z0 + 1);
-
-    const int tid = threadIdx.x;
-    const int cx = tid % G, rp = tid / G;
-    const int32_t x = x0 + 16 * cx;
-    const int32_t y = y0 + rp * RL;               // first output row of the lane
-    const int32_t xe = (cx == 0) ? x0 - 4 : x0 + RHO;
-    const bool is_edge = (cx == 0) || (cx == G - 1);
     const int64_t p1 = P.stride[1], p2 = P.stride[2];
     const int64_t total = p2 * p1;
-    // per-lane 32-bit offsets, inside a plane, of the rows y-1 .. y+RL read
-    // for every plane (rows never read are clamped to 0)
-    uint32_t off[NR], offe[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        const int32_t yy = y - 1 + k;
-        off[k] = yy >= 0 ? (uint32_t)yy * (uint32_t)p1 + (uint32_t)x : 0u;
-        offe[k] = (yy >= 0 && xe >= 0) ? (uint32_t)yy * (uint32_t)p1 + (uint32_t)xe : 0u;
-    }
+    const int tid = threadIdx.x;
 
-    // Raw loads of the rows of plane z the lane needs.
-    auto load_plane = [&](int32_t z, uint32_t (&c)[NR][4], uint32_t (&e)[NR]) {
+    // Chunk k of this lane: staged row r = q / C, chunk column c = q % C,
+    // covering y = y0-1+r, x = x0-4+16c .. +15 (q = tid + k NT < NCH).
+    // Returns the row y, the first x and the in-plane offset of the load
+    // (x clamped to 0 for the left halo chunk of a tile at x0 = 0).
+    auto chunk_geom = [&](int k, int32_t &y, int32_t &xs, uint32_t &off) {
+        const int q = tid + k * NT;
+        const int r = q / C, c = q % C;
+        y = y0 - 1 + r;
+        xs = x0 - 4 + 16 * c;
+        off = (uint32_t)max(y, 0) * (uint32_t)p1 + (uint32_t)max(xs, 0);
+    };
+    // Raw loads of the lane's chunks of plane z (no masking: the loads of a
+    // plane issue back to back).  Chunks that hold no simplex cell, and
+    // planes outside 0..n, are not loaded.
+    auto load_plane = [&](int32_t z, uint4 (&R)[KQ]) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            c[k][0] = c[k][1] = c[k][2] = c[k][3] = 0u;
-            e[k] = 0u;
-        }
-        if ((uint32_t)z > (uint32_t)n) return;      // z < 0 or z > n (uniform)
-        const uint8_t *pl = in + (int64_t)z * p2;    // wave-uniform plane pointer
+        for (int k = 0; k < KQ; ++k) R[k] = make_uint4(0u, 0u, 0u, 0u);
+        if ((uint32_t)z > (uint32_t)n) return;    // uniform
+        const uint8_t *pl = in + (int64_t)z * p2;
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            const int32_t yy = y - 1 + k;
-            if (yy < 0 || yy > n) continue;
-            const int32_t lim = n - z - yy;          // largest x of the row in the simplex
+        for (int k = 0; k < KQ; ++k) {
+            if (NCH % NT != 0 && tid + k * NT >= NCH) continue;
+            int32_t y, xs;
+            uint32_t off;
+            chunk_geom(k, y, xs, off);
+            const int32_t xl = max(xs, 0);
+            if (y < 0 || n - z - y - xl < 0) continue;   // first loaded cell outside
             if constexpr (SAFE) {
-                const int64_t rb = (int64_t)z * p2 + (int64_t)yy * p1;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) c[k][i] = ld_masked(in + rb, x + 4 * i, yy + z, n, total - rb);
-                if (is_edge) e[k] = ld_masked(in + rb, xe, yy + z, n, total - rb);
+                const int64_t rb = (int64_t)z * p2 + (int64_t)y * p1;
+                R[k].x = ld_masked(in + rb, xl, y + z, n, total - rb);
+                R[k].y = ld_masked(in + rb, xl + 4, y + z, n, total - rb);
+                R[k].z = ld_masked(in + rb, xl + 8, y + z, n, total - rb);
+                R[k].w = ld_masked(in + rb, xl + 12, y + z, n, total - rb);
             } else {
-                if (x <= lim) {
-                    const uint4 q = *reinterpret_cast<const uint4 *>(pl + off[k]);
-                    c[k][0] = q.x; c[k][1] = q.y; c[k][2] = q.z; c[k][3] = q.w;
-                }
-                if (is_edge && xe >= 0 && xe <= lim) e[k] = ld_u32(pl + offe[k]);
+                R[k] = *reinterpret_cast<const uint4 *>(pl + off);
             }
         }
     };
-    // Zero the cells outside the simplex, then form the in-plane 3x3 sums of
-    // the lane's RL rows (and their centre rows).
-    auto plane_sums = [&](int32_t z, uint32_t (&c)[NR][4], uint32_t (&e)[NR], uint32_t (&S)[RL][4],
-                          uint32_t (&ctr)[RL][4]) {
-        uint32_t h[NR][4];
+    // Clear the bytes outside the simplex and write the chunks of plane z to
+    // LDS buffer b.  Every chunk slot is written (zeros where nothing was
+    // loaded).
+    auto commit_plane = [&](int32_t z, const uint4 (&R)[KQ], int b) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            if constexpr (!SAFE) {
-                const int32_t v = n - z - (y - 1 + k) - x + 1;
-                if (v < 16) {
+        for (int k = 0; k < KQ; ++k) {
+            if (NCH % NT != 0 && tid + k * NT >= NCH) continue;
+            int32_t y, xs;
+            uint32_t off;
+            chunk_geom(k, y, xs, off);
+            uint32_t w[4] = {R[k].x, R[k].y, R[k].z, R[k].w};
+            if (xs < 0) {                         // loaded from x = 0: shift into place
+                w[3] = w[2];
+                w[2] = w[1];
+                w[1] = w[0];
+                w[0] = 0u;
+            }
+            // cells x_s .. x_s + v - 1 of the chunk are in the simplex
+            const int32_t v = ((uint32_t)z > (uint32_t)n || y < 0) ? 0 : n - z - y - xs + 1;
+            if (v < 16) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int32_t keep = v - 4 * i;
-                        c[k][i] = keep >= 4 ? c[k][i] : (keep <= 0 ? 0u : c[k][i] & ((1u << (8 * keep)) - 1u));
+                for (int i = 0; i < 4; ++i) {
+                    const int32_t keep = v - 4 * i;
+                    w[i] = keep >= 4 ? w[i] : (keep <= 0 ? 0u : w[i] & ((1u << (8 * keep)) - 1u));
+                }
+            }
+            const int q = tid + k * NT;
+            *reinterpret_cast<uint4 *>(&lds[b][(q / C) * PITCH + (q % C) * 16]) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    };
+
+    const int cx = tid % G, rp = tid / G;
+    const int32_t x = x0 + 16 * cx;
+    const int32_t ylane = y0 + rp * RL;           // first output row of the lane
+    // In-plane 3x3 sums of the lane's RL rows from LDS buffer b, and the
+    // centre cells of those rows.
+    auto plane_sums = [&](int b, uint32_t (&S)[RL][4], uint32_t (&ctr)[RL][4]) {
+        uint32_t h[RL + 2][4];
+#pragma unroll
+        for (int jj = 0; jj < RL + 2; ++jj) {
+            const uint8_t *src = &lds[b][(rp * RL + jj) * PITCH + 16 * cx];
+            const uint4 a = *reinterpret_cast<const uint4 *>(src);        // left dword, cells 0..11
+            const uint2 e = *reinterpret_cast<const uint2 *>(src + 16);   // cells 12..15, right dword
+            const uint32_t c[4] = {a.y, a.z, a.w, e.x};
+            hsum16(c, a.x, e.y, h[jj]);
+            if (jj >= 1 && jj <= RL) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ctr[jj - 1][i] = c[i];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RL; ++j) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) S[j][i] = h[j][i] + h[j + 1][i] + h[j + 2][i];
+        }
+    };
+
+    // Two register sets of chunk loads alternate (the plane loop is unrolled
+    // by two), so a set is consumed two planes after its loads were issued
+    // with no register copy in between: a copy would wait for the loads.
+    uint4 RA[KQ], RB[KQ];
+    load_plane(z0 - 1, RA);
+    commit_plane(z0 - 1, RA, 0);
+    load_plane(z0, RA);
+    load_plane(z0 + 1, RB);
+    __syncthreads();
+
+    uint32_t sp[RL][4] = {}, sc[RL][4] = {}, cp[RL][4] = {};
+    const int32_t steps = nz + 2;                 // staged planes z0-1 .. z0+nz
+    // Step i: plane z0-1+i is staged in lds[i & 1] and RX holds plane z0+i.
+    auto step = [&](int32_t i, uint4 (&RX)[KQ]) {
+        uint32_t sn[RL][4], cn[RL][4];
+        plane_sums(i & 1, sn, cn);
+        if (i >= 2) {                             // output plane z0 + i - 2
+            const int32_t z = z0 + i - 2;
+#pragma unroll
+            for (int j = 0; j < RL; ++j) {
+                uint32_t res[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) res[k] = rule_b6s567(sp[j][k] + sc[j][k] + sn[j][k], cp[j][k]);
+                const int32_t yj = ylane + j;
+                const int32_t v = n - z - yj - x + 1;
+                if (v > 0) {
+                    uint8_t *row = out + (int64_t)z * p2 + (int64_t)yj * p1;
+                    if (v >= 16) {
+                        *reinterpret_cast<uint4 *>(row + x) = make_uint4(res[0], res[1], res[2], res[3]);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) st_masked(row, x + 4 * k, yj + z, n, res[k]);
                     }
                 }
-                const int32_t ve = n - z - (y - 1 + k) - xe + 1;
-                if (ve < 4) e[k] = ve <= 0 ? 0u : e[k] & ((1u << (8 * ve)) - 1u);
             }
-            hsum16(c[k], lane_prev<G>(c[k], e[k], cx), lane_next<G>(c[k], e[k], cx), h[k]);
         }
 #pragma unroll
         for (int j = 0; j < RL; ++j) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                S[j][i] = h[j][i] + h[j + 1][i] + h[j + 2][i];
-                ctr[j][i] = c[j + 1][i];
+            for (int k = 0; k < 4; ++k) {
+                sp[j][k] = sc[j][k];
+                sc[j][k] = sn[j][k];
+                cp[j][k] = cn[j][k];
             }
         }
+        if (i + 1 < steps) {
+            commit_plane(z0 + i, RX, (i + 1) & 1);        // staged for step i + 1
+            if (i + 3 < steps) load_plane(z0 + i + 2, RX);   // consumed at step i + 2
+        }
+        __syncthreads();
     };
+    for (int32_t i = 0; i < steps; i += 2) {
+        step(i, RA);
+        if (i + 1 < steps) step(i + 1, RB);
+    }
+}
 
-    // planes z0-1 and z0: the first two in-plane sums
-    uint32_t sp[RL][4], sc[RL][4], cc[RL][4];
-    {
-        uint32_t ca[NR][4], ea[NR], junk[RL][4];
-        load_plane(z0 - 1, ca, ea);
-        plane_sums(z0 - 1, ca, ea, sp, junk);
-        load_plane(z0, ca, ea);
-        plane_sums(z0, ca, ea, sc, cc);
+// The CA3 kernel.  H: grid (map grid, SUB), x-adjacent tiles of one
+// sub-block position run together.  BB: grid (kbox, kbox, kbox * SUB).
+template <int RHO, int RY, int RZ, int RL, bool BB, bool SAFE>
+__global__ __launch_bounds__((RHO / 16) * (RY / RL)) void k_ca3(const Plan P, const uint8_t *__restrict__ in,
+                                                                       uint8_t *__restrict__ out)
+{
+    constexpr int SUB = Ca3Walk<RHO, RY, RZ, RL>::SUB;
+    int32_t t[4] = {0, 0, 0, 0};
+    uint32_t sub;
+    const WgId g = wg_id(P);
+    if (BB) {
+        decode_bb(P, g.x, g.y, g.z / SUB, t);
+        sub = g.z % SUB;
+    } else {
+        if (!decode_h<3>(P, g.x, t)) return;
+        sub = g.y;
     }
-    for (int32_t p = 0; p < nz; ++p) {
-        const int32_t z = z0 + p;                    // output plane
-        uint32_t cn[NR][4], en[NR], sn[RL][4], cnext[RL][4];
-        load_plane(z + 1, cn, en);
-        plane_sums(z + 1, cn, en, sn, cnext);
-#pragma unroll
-        for (int j = 0; j < RL; ++j) {
-            uint32_t res[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) res[i] = rule_b6s567(sp[j][i] + sc[j][i] + sn[j][i], cc[j][i]);
-            // store the lane's cells of row (y + j, z) that lie in the simplex
-            const int32_t yj = y + j;
-            const int32_t v = n - z - yj - x + 1;
-            if (yj <= n && v > 0) {
-                uint8_t *row = out + (int64_t)z * p2 + (int64_t)yj * p1;
-                if (v >= 16) {
-                    *reinterpret_cast<uint4 *>(row + x) = make_uint4(res[0], res[1], res[2], res[3]);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) st_masked(row, x + 4 * i, yj + z, n, res[i]);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                sp[j][i] = sc[j][i];
-                sc[j][i] = sn[j][i];
-                cc[j][i] = cnext[j][i];
-            }
-        }
-    }
+    ca3_tile<RHO, RY, RZ, RL, SAFE>(P, in, out, t, sub);
 }
 
 }  // namespace smap

@@ -6,15 +6,19 @@
 // behind one mutex.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "../../include/simplexmap.h"
+#include "smap_batch.hpp"
 #include "smap_ca2.hpp"
 #include "smap_ca3.hpp"
 #include "smap_plan.hpp"
 #include "smap_point.hpp"
+#include "smap_serve.hpp"
 
 using namespace smap;
 
@@ -46,13 +50,21 @@ constexpr PointShape kPointShapes[] = {
 };
 
 // CA3 shapes: (rho, threads) -> rows RY (y), planes RZ (z), rows per lane RL.
+#ifndef SMAP_CA3_RZ
+#define SMAP_CA3_RZ 32
+#endif
 struct Ca3Shape {
     int rho, wg, ry, rz, rl, sub;
 };
+constexpr int ca3_rz(int rho) { return SMAP_CA3_RZ < rho ? SMAP_CA3_RZ : rho; }
 constexpr Ca3Shape kCa3Shapes[] = {
-    {128, 256, 64, 16, 2, 16}, {128, 128, 32, 16, 2, 32}, {128, 64, 32, 16, 4, 32},
-    {256, 256, 32, 16, 2, 128}, {64, 128, 64, 16, 2, 4},  {64, 64, 64, 16, 4, 4},
-    {32, 64, 32, 16, 1, 2},
+    {128, 256, 64, ca3_rz(128), 2, (128 / 64) * (128 / ca3_rz(128))},
+    {128, 128, 32, ca3_rz(128), 2, (128 / 32) * (128 / ca3_rz(128))},
+    {128, 512, 128, ca3_rz(128), 2, (128 / 128) * (128 / ca3_rz(128))},
+    {256, 256, 32, ca3_rz(256), 2, (256 / 32) * (256 / ca3_rz(256))},
+    {64, 128, 64, ca3_rz(64), 2, (64 / 64) * (64 / ca3_rz(64))},
+    {64, 256, 64, ca3_rz(64), 1, (64 / 64) * (64 / ca3_rz(64))},
+    {32, 64, 32, ca3_rz(32), 1, (32 / 32) * (32 / ca3_rz(32))},
 };
 
 // op class: 0 = pointwise (MAP/ACCUM/HITS/HASH), 1 = CA2, 2 = CA3
@@ -61,7 +73,7 @@ int op_class(int op) { return op == OP_CA2 ? 1 : (op == OP_CA3 ? 2 : 0); }
 TileCfg default_tile(int m, int cls)
 {
     if (cls == 1) return {1024, 64, 64};
-    if (cls == 2) return {128, 256, 16};
+    if (cls == 2) return {128, 256, (128 / 64) * (128 / ca3_rz(128))};
     for (const PointShape &c : kPointShapes)  // the first listed shape of an m is its default
         if (c.m == m) return {c.rho, c.wg, c.sub};
     return {0, 0, 1};
@@ -143,12 +155,9 @@ bool box_elems(int m, int64_t n, int64_t *out)
 
 // Plan lookup; also checks that in-tile offsets fit the kernels' 32-bit
 // lane offsets.
-int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C, TileCfg *tc)
+// Plan of (m, n, beta, tile t, H|BB, op class) from the cache (g_mu held).
+int plan_for(int m, int64_t n, int beta, bool bb, int cls, const TileCfg &t, Plan *P, PlanCounts *C)
 {
-    const int cls = op_class(op);
-    std::lock_guard<std::mutex> lk(g_mu);
-    const TileCfg t = tile_for(m, cls);
-    *tc = t;
     auto key = std::make_tuple(m, n, bb ? 0 : beta, t.rho, bb ? 1 : 0, cls);
     auto it = g_plans.find(key);
     if (it == g_plans.end()) {
@@ -182,6 +191,16 @@ int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C
     *P = it->second.plan;
     if (C) *C = it->second.counts;
     return it->second.status;
+}
+
+// Plan for a launch with the current tile of (m, op class).
+int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C, TileCfg *tc)
+{
+    const int cls = op_class(op);
+    std::lock_guard<std::mutex> lk(g_mu);
+    const TileCfg t = tile_for(m, cls);
+    *tc = t;
+    return plan_for(m, n, beta, bb, cls, t, P, C);
 }
 
 int check_op(int m, int64_t n, int op)
@@ -315,13 +334,13 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
             else                                                                                  \
                 hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, false>), grid, dim3(WG), 0, s, PL, i8, o8); \
             return kOk;
-        SMAP_CA3(128, 256, 64, 16, 2)
-        SMAP_CA3(128, 128, 32, 16, 2)
-        SMAP_CA3(128, 64, 32, 16, 4)
-        SMAP_CA3(256, 256, 32, 16, 2)
-        SMAP_CA3(64, 128, 64, 16, 2)
-        SMAP_CA3(64, 64, 64, 16, 4)
-        SMAP_CA3(32, 64, 32, 16, 1)
+        SMAP_CA3(128, 256, 64, ca3_rz(128), 2)
+        SMAP_CA3(128, 128, 32, ca3_rz(128), 2)
+        SMAP_CA3(128, 512, 128, ca3_rz(128), 2)
+        SMAP_CA3(256, 256, 32, ca3_rz(256), 2)
+        SMAP_CA3(64, 128, 64, ca3_rz(64), 2)
+        SMAP_CA3(64, 256, 64, ca3_rz(64), 1)
+        SMAP_CA3(32, 64, 32, ca3_rz(32), 1)
 #undef SMAP_CA3
         }
         return kEunsupported;
@@ -350,6 +369,152 @@ int do_launch(int m, int64_t n, int r, int beta, int op, const void *in, void *o
     rc = bb ? dispatch<true>(m, op, tc, P, in, out, s) : dispatch<false>(m, op, tc, P, in, out, s);
     if (rc != kOk) return rc;
     return hipGetLastError() == hipSuccess ? kOk : kEhip;
+}
+
+// ---- batched launches ------------------------------------------------------
+
+// Batched tile shapes: CA2 rho 256 (4 waves, 16 rows per segment, one
+// workgroup per tile); CA3 rho 64 (128 threads, 64 rows, 16 planes per
+// sub-block, 2 rows per lane).
+constexpr TileCfg kBatchCa2 = {256, 256, 1};
+constexpr int kBatchCa3Ry = 64, kBatchCa3Rz = 16, kBatchCa3Rl = 2;
+constexpr TileCfg kBatchCa3 = {64, 128, (64 / kBatchCa3Ry) * (64 / kBatchCa3Rz)};
+constexpr int kBatchMaxJobs = 4096;   // jobs per launch (table capacity)
+constexpr int kBatchSlots = 16;       // table buffers per device
+
+// One table buffer: start[kBatchMaxJobs + 1] (padded to 256 bytes), then
+// the BatchJob array.  Pinned host staging plus its device copy; `ev`
+// marks the end of the launch that last read it.
+constexpr size_t kStartBytes = ((sizeof(uint32_t) * (kBatchMaxJobs + 1) + 255) / 256) * 256;
+constexpr size_t kSlotBytes = kStartBytes + sizeof(BatchJob) * kBatchMaxJobs;
+
+struct BatchRing {
+    uint8_t *host = nullptr;
+    uint8_t *dev = nullptr;
+    hipEvent_t ev[kBatchSlots] = {};
+    bool used[kBatchSlots] = {};
+    int next = 0;
+};
+std::mutex g_batch_mu;
+std::map<int, BatchRing> g_rings;  // per device
+
+int ring_for_device(BatchRing **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kEhip;
+    BatchRing &R = g_rings[dev];
+    if (!R.dev) {
+        if (hipHostMalloc((void **)&R.host, kSlotBytes * kBatchSlots, hipHostMallocDefault) != hipSuccess)
+            return kEhip;
+        if (hipMalloc((void **)&R.dev, kSlotBytes * kBatchSlots) != hipSuccess) {
+            (void)hipHostFree(R.host);
+            R.host = nullptr;
+            return kEhip;
+        }
+        for (int i = 0; i < kBatchSlots; ++i) {
+            if (hipEventCreateWithFlags(&R.ev[i], hipEventDisableTiming) != hipSuccess) return kEhip;
+        }
+    }
+    *out = &R;
+    return kOk;
+}
+
+struct BatchItem {
+    Plan P;
+    const uint8_t *in;
+    uint8_t *out;
+    uint32_t nwg;  // workgroups of the job
+};
+
+// One launch of a kernel class over items[0..cnt): fill a ring slot, copy
+// it to the device, launch.
+int launch_batch_chunk(BatchRing &R, int kind, const BatchItem *items, int cnt, hipStream_t s)
+{
+    const int slot = R.next;
+    R.next = (R.next + 1) % kBatchSlots;
+    if (R.used[slot] && hipEventSynchronize(R.ev[slot]) != hipSuccess) return kEhip;
+    uint8_t *h = R.host + (size_t)slot * kSlotBytes;
+    uint8_t *d = R.dev + (size_t)slot * kSlotBytes;
+    uint32_t *start = reinterpret_cast<uint32_t *>(h);
+    BatchJob *jobs = reinterpret_cast<BatchJob *>(h + kStartBytes);
+    uint64_t acc = 0;
+    for (int i = 0; i < cnt; ++i) {
+        start[i] = (uint32_t)acc;
+        jobs[i].P = items[i].P;
+        jobs[i].in = items[i].in;
+        jobs[i].out = items[i].out;
+        acc += items[i].nwg;
+    }
+    start[cnt] = (uint32_t)acc;
+    if (acc == 0) return kOk;
+    if (acc > kMaxWorkgroups) return kErange;
+    const size_t bytes = kStartBytes + sizeof(BatchJob) * (size_t)cnt;
+    if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return kEhip;
+    const uint32_t *dstart = reinterpret_cast<const uint32_t *>(d);
+    const BatchJob *djobs = reinterpret_cast<const BatchJob *>(d + kStartBytes);
+    const uint32_t nwg = (uint32_t)acc, nj = (uint32_t)cnt;
+    switch (kind) {
+    case 0:
+        hipLaunchKernelGGL((k_ca2_batch<256, 4, 16, 2, false>), dim3(nwg), dim3(256), 0, s, dstart, djobs, nj, nwg);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_ca2_batch<256, 4, 16, 2, true>), dim3(nwg), dim3(256), 0, s, dstart, djobs, nj, nwg);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_ca3_batch<64, kBatchCa3Ry, kBatchCa3Rz, kBatchCa3Rl, false>), dim3(nwg),
+                           dim3(kBatchCa3.wg), 0, s, dstart, djobs, nj, nwg);
+        break;
+    default:
+        hipLaunchKernelGGL((k_ca3_batch<64, kBatchCa3Ry, kBatchCa3Rz, kBatchCa3Rl, true>), dim3(nwg),
+                           dim3(kBatchCa3.wg), 0, s, dstart, djobs, nj, nwg);
+        break;
+    }
+    if (hipGetLastError() != hipSuccess) return kEhip;
+    if (hipEventRecord(R.ev[slot], s) != hipSuccess) return kEhip;
+    R.used[slot] = true;
+    return kOk;
+}
+
+int batch_launch(const simplex_job *jobs, int32_t njobs, void *stream)
+{
+    if (njobs < 0 || (njobs > 0 && !jobs)) return kEinval;
+    if (njobs == 0) return kOk;
+    // kinds: 0 CA2, 1 CA2 (n < 15), 2 CA3, 3 CA3 (n < 15)
+    std::vector<BatchItem> items[4];
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (int32_t i = 0; i < njobs; ++i) {
+            const simplex_job &J = jobs[i];
+            const bool ca2 = J.m == 2 && J.op == OP_CA2, ca3 = J.m == 3 && J.op == OP_CA3;
+            if (!ca2 && !ca3) return kEinval;
+            int rc = check_op(J.m, J.n, J.op);
+            if (rc != kOk) return rc;
+            rc = check_buffers(J.m, J.n, J.op, J.buf_in, J.buf_out);
+            if (rc != kOk) return rc;
+            const TileCfg &t = ca2 ? kBatchCa2 : kBatchCa3;
+            BatchItem it{};
+            rc = plan_for(J.m, J.n, 2, false, ca2 ? 1 : 2, t, &it.P, nullptr);
+            if (rc != kOk) return rc;
+            it.in = (const uint8_t *)J.buf_in;
+            it.out = (uint8_t *)J.buf_out;
+            it.nwg = it.P.total * (uint32_t)t.sub;
+            items[(ca2 ? 0 : 2) + (J.n < 15 ? 1 : 0)].push_back(it);
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchRing *R = nullptr;
+    int rc = ring_for_device(&R);
+    if (rc != kOk) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    for (int kind = 0; kind < 4; ++kind) {
+        const std::vector<BatchItem> &v = items[kind];
+        for (size_t o = 0; o < v.size(); o += kBatchMaxJobs) {
+            const int cnt = (int)std::min<size_t>(kBatchMaxJobs, v.size() - o);
+            rc = launch_batch_chunk(*R, kind, v.data() + o, cnt, s);
+            if (rc != kOk) return rc;
+        }
+    }
+    return kOk;
 }
 
 }  // namespace
@@ -465,6 +630,41 @@ int simplex_set_tile(int m, int op, int rho, int wg_threads)
     if (wg_threads != 0 && wg_threads != wg) return kEunsupported;
     g_tiles[{m, cls}] = TileCfg{rho, wg, sub};
     return kOk;
+}
+
+int simplex_batch_launch(const struct simplex_job *jobs, int32_t njobs, void *stream)
+{
+    return batch_launch(jobs, njobs, stream);
+}
+
+int simplex_serve_run(const struct simplex_serve_job *jobs, int32_t njobs, void *arena,
+                      uint64_t arena_bytes, int32_t mode, int32_t max_inflight, int32_t keep_outputs,
+                      struct simplex_serve_record *records)
+{
+    if (njobs < 0 || (njobs > 0 && (!jobs || !arena))) return kEinval;
+    if (mode != SMAP_SERVE_SEQUENTIAL && mode != SMAP_SERVE_BATCHED) return kEinval;
+    if (mode == SMAP_SERVE_BATCHED && max_inflight < 1) return kEinval;
+    uint64_t need_all = 0;
+    for (int32_t i = 0; i < njobs; ++i) {
+        const simplex_serve_job &J = jobs[i];
+        const bool ok = (J.m == 2 && J.op == OP_CA2) || (J.m == 3 && J.op == OP_CA3);
+        if (!ok || J.n < 0 || !J.buf_in) return kEinval;
+        if (!(J.arrival_s >= 0.0) || (i > 0 && J.arrival_s < jobs[i - 1].arrival_s)) return kEinval;
+        int64_t elems;
+        if (!box_elems(J.m, J.n, &elems)) return kErange;
+        const uint64_t b = Arena::round((uint64_t)elems);
+        if (b > (arena_bytes & ~uint64_t(255))) return kEinval;   // could never be admitted
+        need_all += b;
+    }
+    if (keep_outputs && need_all > (arena_bytes & ~uint64_t(255))) return kEinval;
+    if (njobs == 0) return kOk;
+    std::vector<simplex_serve_record> local;
+    if (!records) {
+        local.resize((size_t)njobs);
+        records = local.data();
+    }
+    for (int32_t i = 0; i < njobs; ++i) records[i] = simplex_serve_record{-1.0, -1.0, -1.0, 0, -1, kOk};
+    return serve_run(jobs, njobs, (uint8_t *)arena, arena_bytes, mode, max_inflight, keep_outputs, records);
 }
 
 const char *simplex_strerror(int status)

@@ -104,7 +104,7 @@ def test_set_tile_validation():
     with pytest.raises(smap.SimplexMapError):
         smap.set_tile(3, "ca3", 32, 256)
     with pytest.raises(smap.SimplexMapError):
-        smap.set_tile(3, "ca3", 64, 256)
+        smap.set_tile(3, "ca3", 64, 512)
     smap.set_tile(2, "ca2", 128)
     assert smap.plan_info(2, 1000, "ca2")["rho"] == 128
     assert smap.plan_info(2, 1000, "ca2")["wg_threads"] == 128
@@ -125,3 +125,38 @@ def test_plan_info_fields():
     assert bb["launched_tiles"] == 17 * 17 and bb["use_bb"] == 1
     assert smap.plan_info(4, 128, "hash")["beta"] == 3
     assert smap.plan_info(4, 128, "hash", beta=4)["beta"] == 4
+
+
+def test_batch_launch_argument_errors():
+    """simplex_batch_launch validates every job before enqueueing anything."""
+    E = smap.EINVAL
+    assert smap.batch_launch_raw([], 0) == smap.OK            # empty batch: no-op
+    assert smap.batch_launch_raw([], -1) == E
+    assert smap.lib().simplex_batch_launch(None, 3, None) == E
+    good = (2, "ca2", 100, 4096, 1 << 20)
+    assert smap.batch_launch_raw([(2, "ca3", 10, 4096, 1 << 20)]) == E   # CA3 needs m = 3
+    assert smap.batch_launch_raw([(3, "ca2", 10, 4096, 1 << 20)]) == E
+    assert smap.batch_launch_raw([(2, "accum", 10, 4096, 1 << 20)]) == E  # automata only
+    assert smap.batch_launch_raw([good, (2, "ca2", -1, 4096, 1 << 20)]) == E
+    assert smap.batch_launch_raw([good, (2, "ca2", 100, 0, 1 << 20)]) == E  # NULL input
+    assert smap.batch_launch_raw([good, (2, "ca2", 100, 4096, 4096 + 50)]) == E  # overlap
+
+
+def test_serve_run_argument_errors():
+    """simplex_serve_run validates the whole job stream before any work."""
+    E = smap.EINVAL
+    arena, size = 1 << 12, 1 << 20
+    assert smap.serve_run_raw([], 0, 0, smap.SERVE_BATCHED)[0] == smap.OK
+    job = (2, "ca2", 100, 4096, 0.0)
+    assert smap.serve_run_raw([job], arena, size, 7)[0] == E                    # bad mode
+    assert smap.serve_run_raw([job], arena, size, smap.SERVE_BATCHED, 0)[0] == E  # max_inflight
+    assert smap.serve_run_raw([job], 0, size, smap.SERVE_BATCHED)[0] == E       # no arena
+    assert smap.serve_run_raw([(2, "ca2", 100, 4096, 1.0), (2, "ca2", 100, 4096, 0.5)],
+                              arena, size, smap.SERVE_BATCHED)[0] == E          # arrivals out of order
+    assert smap.serve_run_raw([(2, "ca2", 100, 4096, -1.0)], arena, size, smap.SERVE_BATCHED)[0] == E
+    assert smap.serve_run_raw([(2, "ca2", 2000, 4096, 0.0)], arena, size, smap.SERVE_BATCHED)[0] == E  # never fits
+    assert smap.serve_run_raw([(3, "ca2", 10, 4096, 0.0)], arena, size, smap.SERVE_BATCHED)[0] == E
+    assert smap.serve_run_raw([(2, "ca2", 10, 0, 0.0)], arena, size, smap.SERVE_BATCHED)[0] == E
+    # keep_outputs needs room for every output at once
+    two = [(2, "ca2", 730, 4096, 0.0), (2, "ca2", 730, 4096, 0.0)]
+    assert smap.serve_run_raw(two, arena, size, smap.SERVE_BATCHED, 2, True)[0] == E

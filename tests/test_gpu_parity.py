@@ -165,7 +165,7 @@ def test_ca2_parity(smap):
 CA3_SIZES = list(range(0, 41)) + [62, 63, 64, 65, 66, 95, 96, 97, 127, 128, 150]
 
 
-CA3_TILES = [(128, 256), (128, 128), (128, 64), (256, 256), (64, 128), (64, 64), (32, 64)]
+CA3_TILES = [(128, 256), (128, 128), (128, 512), (256, 256), (64, 128), (64, 256), (32, 64)]
 
 
 def test_ca3_parity(smap):
