@@ -92,6 +92,81 @@ def copy_probe(nbytes, steps, stream):
             "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def bench_serve(args):
+    """The serving workload: a stream of one-step automaton jobs (60 % m = 2
+    with n log-uniform in [64, 4096], 40 % m = 3 with n log-uniform in
+    [32, 512]), inputs resident in HBM, outputs in an arena of --budget-gib.
+    Saturated throughput (every job at t = 0) of sequential plain-H launches
+    and of continuous batching, then both at a Poisson load of --load times
+    the sequential saturated rate, with p50/p99 latency (arrival to the end
+    of the job's launch, device events)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import simplex_inputs as si
+    from paper_2208_11617_amd import binding as smap
+
+    torch.cuda.set_device(0)
+    jobs0 = si.serve_trace(args.jobs, None)
+    shapes = sorted(set((m, n) for m, n, _ in jobs0))
+    log(f"serving: {args.jobs} jobs, {len(shapes)} distinct sizes; generating inputs")
+    inputs = {(m, n): si.box_torch(m, n, "bern", si.serve_seed(m, n), p=si.SERVE["p"], device="cuda")
+              for m, n in shapes}
+    arena = torch.empty(int(args.budget_gib * (1 << 30)), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    cells = {mn: math.comb(mn[1] + mn[0], mn[0]) for mn in shapes}
+    op = {2: "ca2", 3: "ca3"}
+
+    def replay(trace, mode):
+        recs = smap.serve_run([(m, op[m], n, inputs[(m, n)], t) for m, n, t in trace], arena, mode,
+                              max_inflight=args.max_inflight)
+        lat = np.array([r["done_s"] - t for r, (_, _, t) in zip(recs, trace)])
+        span = max(r["done_s"] for r in recs) - min(t for _, _, t in trace)
+        useful = sum(cells[(m, n)] for m, n, _ in trace)
+        return {"jobs_per_s": len(trace) / span, "elements_per_s": useful / span,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3), "launches": int(max(r["batch"] for r in recs)) + 1,
+                "makespan_s": span}
+
+    res = {}
+    for name, mode in (("sequential", smap.SERVE_SEQUENTIAL), ("batched", smap.SERVE_BATCHED)):
+        for _ in range(args.warmup_replays):
+            replay(jobs0, mode)
+        log(f"saturated replay: {name}")
+        res[f"saturated_{name}"] = replay(jobs0, mode)
+    rate = args.load * res["saturated_sequential"]["jobs_per_s"]
+    trace = si.serve_trace(args.jobs, rate)
+    for name, mode in (("sequential", smap.SERVE_SEQUENTIAL), ("batched", smap.SERVE_BATCHED)):
+        log(f"Poisson replay at {rate:.0f} jobs/s: {name}")
+        res[f"load_{name}"] = replay(trace, mode)
+    sat_b = res["saturated_batched"]
+    out = {
+        "metric": "useful simplex elements/s (serving, continuous batching, saturated)",
+        "value": sat_b["elements_per_s"],
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": args.warmup_replays,
+        "ms_per_step": sat_b["makespan_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (seeded splitmix64 cells, seeded Poisson arrivals)",
+        "config": {"workload": f"c5: serving, {args.jobs} one-step automaton jobs, "
+                               f"{len(shapes)} sizes, budget {args.budget_gib} GiB",
+                   "jobs": args.jobs, "budget_gib": args.budget_gib, "load": args.load,
+                   "offered_rate_jobs_per_s": rate, "max_inflight": args.max_inflight},
+        "serving": res,
+        "batched_vs_sequential_saturated": sat_b["jobs_per_s"] / res["saturated_sequential"]["jobs_per_s"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The oracle, single-threaded, on a bounded sample of the same workload:
     whole slabs of the outermost coordinate x_m, starting at x_m = 0, until
@@ -136,11 +211,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--jobs", type=int, default=10000, help="c5: jobs in the stream")
+    ap.add_argument("--budget-gib", type=float, default=8.0, help="c5: output arena")
+    ap.add_argument("--load", type=float, default=0.8, help="c5: offered load / sequential rate")
+    ap.add_argument("--max-inflight", type=int, default=2, help="c5: batches in flight")
+    ap.add_argument("--warmup-replays", type=int, default=1, help="c5: untimed replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-bb", action="store_true", help="skip timing the BB baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the plain-copy probe")
     ap.add_argument("--beta", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick rho / workgroup size / beta for the H launch by timing first")
+    ap.add_argument("--tune-cache", default=None, help="autotune result file (read and appended)")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="time H as replays of a captured graph of this many launches")
+    ap.add_argument("--op", default=None, choices=["map", "accum", "hash", "hits"],
+                    help="run this per-element op on the workload's m and n instead of its own")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -148,12 +235,19 @@ def main():
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c5":
+        bench_serve(args)
+        return
+
     import torch
 
     import simplex_inputs as si
     from paper_2208_11617_amd import binding as smap
 
-    w = si.WORKLOADS[args.workload]
+    w = dict(si.WORKLOADS[args.workload])
+    if args.op is not None and args.op != w["op"]:
+        # the same domain with another per-element op (MAP shows the map alone)
+        w.update(op=args.op, dist="u31" if args.op == "accum" else None, p=None)
     m, n, op = w["m"], w["n"], w["op"]
     u8 = op.startswith("ca")
     dev = torch.device("cuda:0")
@@ -175,13 +269,33 @@ def main():
                 launch(m, n, op, src, dst, stream=stream)
             elif op == "accum":
                 launch(m, n, op, bufs[0], out_a, stream=stream)
+            elif op == "map":
+                launch(m, n, op, None, None, stream=stream)
             else:
                 launch(m, n, op, None, out_a, stream=stream)
         return fn
 
+    tuned = None
+    if args.autotune:
+        log("autotuning the H launch")
+        src = bufs[0] if bufs else None
+        tuned = smap.autotune(m, n, op, src, out_a if op != "map" else None, reps=20,
+                              cache_path=args.tune_cache, stream=stream)
+        log(f"tuned: {tuned}")
     h_launch = lambda *a, **k: smap.map_launch(*a, beta=args.beta, **k)  # noqa: E731
-    log(f"timing H: {args.warmup} warmup + {args.steps} steps")
-    h_ms = time_launches(step_fn(h_launch), args.steps, args.warmup, stream)
+    if args.graph > 0:
+        # one replay = args.graph launches (automata: ping-pong, pointwise: repeated)
+        K = args.graph if not u8 else args.graph + (args.graph % 2)
+        src = bufs[0] if bufs else None
+        dst = None if op == "map" else out_a
+        g = smap.Graph(m, n, op, src, dst, steps=K, beta=args.beta)
+        reps = max(1, args.steps // K)
+        log(f"timing H as graph replays: {reps} x {K} launches")
+        h_ms = time_launches(lambda i: g.launch(stream), reps, max(1, args.warmup // K), stream) / K
+        g.close()
+    else:
+        log(f"timing H: {args.warmup} warmup + {args.steps} steps")
+        h_ms = time_launches(step_fn(h_launch), args.steps, args.warmup, stream)
     bb_ms = None
     if not args.no_bb:
         log("timing BB")
@@ -192,7 +306,7 @@ def main():
         log("timing a plain copy of the same byte count")
         copy = copy_probe(max(useful * BYTES_PER_ELEMENT[op] // 2, 1 << 20), 20, stream)
 
-    info_h = smap.plan_info(m, n, op, beta=args.beta)
+    info_h = smap.plan_info(m, n, op, beta=tuned["beta"] if tuned else args.beta)
     info_bb = smap.plan_info(m, n, op, use_bb=True)
     alg_bytes = useful * BYTES_PER_ELEMENT[op]
     achieved = alg_bytes / (h_ms * 1e-3) / 1e9
@@ -214,7 +328,7 @@ def main():
         "data": "synthetic (seeded splitmix64)",
         "config": {"workload": f"{args.workload}: m={m} n={n} op={op}", "m": m, "n": n,
                    "op": op, "useful_elements": useful, "rho": info_h["rho"],
-                   "beta": info_h["beta"]},
+                   "beta": info_h["beta"], "autotuned": tuned, "graph_launches": args.graph or None},
         "hbm_gbs_algorithmic": achieved,
         "bb": None if bb_ms is None else {
             "ms_per_step": bb_ms, "value": useful / (bb_ms * 1e-3),
@@ -239,6 +353,8 @@ def main():
         "copy": copy,
         "cpu_baseline": None,
     }
+    if op == "map":
+        res["roofline"] = None   # the map alone moves no bytes: see tiles and timings
     if not args.no_cpu:
         log("cpu_baseline: oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(w)

@@ -155,12 +155,70 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
  *              128 (128).
  *   Large tiles are split into sub-blocks of rows (and planes), one
  *   workgroup each (wgs_per_tile in the plan info).
- *   CA3 (m=3): rho 128 (256 threads; 128 or 64), 256 (256), 64 (128 or 64),
- *              32 (64).
+ *   CA3 (m=3): rho 128 (256 threads; 128 or 512), 256 (256), 64 (128 or
+ *              256), 32 (64).
  * wg_threads = 0 picks the first listed size; any other value must be one
  * of the listed sizes.
  */
 int simplex_set_tile(int m, int op, int rho, int wg_threads);
+
+/* ---- autotuning and graphs ------------------------------------------------
+ *
+ * Theorem 3 (Section 6) frames the choice of the scale and replication
+ * parameters as an optimisation; here the choice of (beta, rho, workgroup
+ * size) for one (m, n, op) is made by measurement.
+ */
+struct simplex_tune_result {
+    int32_t rho;
+    int32_t wg_threads;
+    int32_t beta;
+    float us;             /* mean duration of one H launch, microseconds */
+};
+
+/*
+ * Times every compiled (rho, workgroup size) of (m, op) -- and beta 3 and 4
+ * for m = 4 -- with `reps` H launches each (after 2 warm-up launches) on
+ * `stream`, picks the fastest, and installs it for later H launches of this
+ * (m, n, op class) in this process (the tile of simplex_set_tile still
+ * applies to other n, and to BB).  A later simplex_map_launch with beta = 0
+ * uses the tuned beta.  Buffers as for simplex_map_launch; for the automata
+ * every timed launch steps buf_in into buf_out (so buf_out ends with one
+ * step of buf_in); ACCUM must not run in place here (buf_in != buf_out).
+ * Synchronises `stream`.
+ *
+ * cache_path (may be NULL): a text file of earlier results, one line per
+ * (device, m, n, op).  If it holds this key, that result is installed and
+ * returned with no timing; otherwise the new result is appended.
+ *
+ * Errors as for simplex_map_launch; reps < 1 gives SMAP_EINVAL; a cache
+ * file that cannot be written gives SMAP_EINVAL after installing the result.
+ */
+int simplex_autotune(int m, int64_t n, int op, const void *buf_in, void *buf_out, int32_t reps,
+                     const char *cache_path, void *stream, struct simplex_tune_result *best);
+
+/*
+ * Drops every tuned entry (simplex_autotune) of this process.
+ */
+int simplex_autotune_reset(void);
+
+/*
+ * Captures `steps` H launches of op over (m, n) into a HIP graph (an
+ * executable graph instance, *graph).  Pointwise ops repeat the same launch
+ * (ACCUM in place adds `steps` per replay); the automata alternate
+ * buf_in -> buf_out, buf_out -> buf_in, ... (an even `steps` leaves the
+ * result in buf_in).  The capture uses the tile and plan current at
+ * creation.  Nothing runs until simplex_graph_launch.  No memset nodes are
+ * recorded.  Errors as for simplex_map_launch; steps < 1 or a NULL graph
+ * gives SMAP_EINVAL; a capture or instantiation failure gives SMAP_EHIP.
+ */
+int simplex_graph_create(int m, int64_t n, int r, int beta, int op, const void *buf_in, void *buf_out,
+                         int32_t steps, void **graph);
+
+/* Enqueues one replay of the graph on `stream`. */
+int simplex_graph_launch(void *graph, void *stream);
+
+/* Frees the graph (after its replays have finished). NULL is a no-op. */
+int simplex_graph_destroy(void *graph);
 
 /* Static, human-readable text for a status code. */
 const char *simplex_strerror(int status);
@@ -224,12 +282,15 @@ struct simplex_serve_job {
                              non-decreasing over the job array */
 };
 
-/* What happened to one job (times in seconds after the start of the run,
- * measured with device events for the completion). */
+/* What happened to one job, in seconds after the start of the run.  Host
+ * clock times are exact; done_s comes from a device event and is placed on
+ * the host clock through the start event (whose own time is taken as the
+ * midpoint of its record-and-wait, an uncertainty of a few microseconds). */
 struct simplex_serve_record {
-    double admit_s;       /* output memory granted */
-    double launch_s;      /* its launch enqueued */
-    double done_s;        /* its launch finished on the device */
+    double admit_s;       /* output memory granted (host) */
+    double launch_s;      /* its launch enqueued (host) */
+    double done_s;        /* its launch finished on the device (device event) */
+    double release_s;     /* completion seen and memory returned (host) */
     uint64_t out_offset;  /* byte offset of its output in the arena */
     int32_t batch;        /* index of the launch group that ran it */
     int32_t status;       /* SMAP_OK, or the error of its launch */

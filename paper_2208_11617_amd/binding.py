@@ -21,7 +21,9 @@ OPS = {"map": OP_MAP, "accum": OP_ACCUM, "hits": OP_HITS, "hash": OP_HASH,
 # names declared in include/simplexmap.h
 EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_plan_info", "simplex_plan_tiles", "simplex_set_tile",
-           "simplex_strerror", "simplex_batch_launch", "simplex_serve_run")
+           "simplex_strerror", "simplex_batch_launch", "simplex_serve_run",
+           "simplex_autotune", "simplex_autotune_reset", "simplex_graph_create",
+           "simplex_graph_launch", "simplex_graph_destroy")
 
 SERVE_SEQUENTIAL, SERVE_BATCHED = 0, 1
 
@@ -73,8 +75,15 @@ class ServeJob(ctypes.Structure):
 class ServeRecord(ctypes.Structure):
     """struct simplex_serve_record"""
     _fields_ = [("admit_s", ctypes.c_double), ("launch_s", ctypes.c_double),
-                ("done_s", ctypes.c_double), ("out_offset", ctypes.c_uint64),
+                ("done_s", ctypes.c_double), ("release_s", ctypes.c_double),
+                ("out_offset", ctypes.c_uint64),
                 ("batch", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    """struct simplex_tune_result"""
+    _fields_ = [("rho", ctypes.c_int32), ("wg_threads", ctypes.c_int32), ("beta", ctypes.c_int32),
+                ("us", ctypes.c_float)]
 
 
 _lib = None
@@ -108,6 +117,17 @@ def lib():
     L.simplex_serve_run.argtypes = [ctypes.POINTER(ServeJob), ctypes.c_int32, vp, u64, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ServeRecord)]
     L.simplex_serve_run.restype = ci
+    L.simplex_autotune.argtypes = [ci, i64, ci, vp, vp, ctypes.c_int32, ctypes.c_char_p, vp,
+                                   ctypes.POINTER(TuneResult)]
+    L.simplex_autotune.restype = ci
+    L.simplex_autotune_reset.argtypes = []
+    L.simplex_autotune_reset.restype = ci
+    L.simplex_graph_create.argtypes = [ci, i64, ci, ci, ci, vp, vp, ctypes.c_int32, ctypes.POINTER(vp)]
+    L.simplex_graph_create.restype = ci
+    L.simplex_graph_launch.argtypes = [vp, vp]
+    L.simplex_graph_launch.restype = ci
+    L.simplex_graph_destroy.argtypes = [vp]
+    L.simplex_graph_destroy.restype = ci
     L.simplex_strerror.argtypes = [ci]
     L.simplex_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -232,3 +252,49 @@ def serve_run(jobs, arena, mode, max_inflight=2, keep_outputs=False):
     rc, recs = serve_run_raw(jobs, arena.data_ptr(), arena.numel(), mode, max_inflight, keep_outputs)
     _check(rc, "simplex_serve_run")
     return recs
+
+
+def autotune_raw(m, n, op, in_ptr, out_ptr, reps=20, cache_path=None, stream_ptr=None):
+    """Status-returning autotune; returns (status, result dict)."""
+    r = TuneResult()
+    rc = lib().simplex_autotune(m, n, _op(op), in_ptr, out_ptr, reps,
+                                None if cache_path is None else cache_path.encode(), stream_ptr,
+                                ctypes.byref(r))
+    return rc, {f: getattr(r, f) for f, _ in TuneResult._fields_}
+
+
+def autotune(m, n, op, buf_in=None, buf_out=None, reps=20, cache_path=None, stream=None) -> dict:
+    """Pick (rho, workgroup size, beta) for H launches of (m, n, op) by timing."""
+    r = TuneResult()
+    _check(lib().simplex_autotune(m, n, _op(op), _ptr(buf_in), _ptr(buf_out), reps,
+                                  None if cache_path is None else cache_path.encode(),
+                                  _stream(stream), ctypes.byref(r)), "simplex_autotune")
+    return {f: getattr(r, f) for f, _ in TuneResult._fields_}
+
+
+def autotune_reset() -> None:
+    _check(lib().simplex_autotune_reset(), "simplex_autotune_reset")
+
+
+class Graph:
+    """A captured run of `steps` H launches (simplex_graph_create)."""
+
+    def __init__(self, m, n, op, buf_in=None, buf_out=None, steps=1, r=0, beta=0):
+        h = ctypes.c_void_p()
+        _check(lib().simplex_graph_create(m, n, r, beta, _op(op), _ptr(buf_in), _ptr(buf_out), steps,
+                                          ctypes.byref(h)), "simplex_graph_create")
+        self.handle = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib().simplex_graph_launch(self.handle, _stream(stream)), "simplex_graph_launch")
+
+    def close(self) -> None:
+        if self.handle:
+            _check(lib().simplex_graph_destroy(self.handle), "simplex_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -249,28 +249,28 @@ __device__ __forceinline__ void ca2_tile(const Plan &P, const uint8_t *__restric
         hsum16(cc, lane_prev<S>(cc, eb, sl), lane_next<S>(cc, eb, sl), hc);
     }
 
-    // Blocks of D output rows: issue the D row loads the block needs (rows
-    // r0+1 .. r0+D, independent, so D rows per wave are in flight), then
-    // mask, sum and store.  `rows` is wave-uniform, so the guards are scalar
-    // branches.
-    for (int32_t r0 = 0; r0 < rows; r0 += D) {
-        uint32_t cn[D][4], en[D];
-        if constexpr (SAFE) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) load_safe(r0 + 1 + k, cn[k], en[k]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < D; ++k) load_raw(r0 + 1 + k, cn[k], en[k]);
-        }
+    // Blocks of D output rows; block r0 needs rows r0+1 .. r0+D.  The loads
+    // of the next block are issued before the current block is summed, into
+    // the other of two register sets (the loop is unrolled by two, so no
+    // register copy waits for a load).  `rows` is wave-uniform, so the
+    // guards are scalar branches.
+    auto load_block = [&](int32_t r0, uint32_t (&c)[D][4], uint32_t (&e)[D]) {
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            if constexpr (!SAFE) mask_row(r0 + 1 + k, cn[k], en[k]);
+            if constexpr (SAFE) load_safe(r0 + 1 + k, c[k], e[k]);
+            else load_raw(r0 + 1 + k, c[k], e[k]);
+        }
+    };
+    auto sum_block = [&](int32_t r0, uint32_t (&c)[D][4], uint32_t (&e)[D]) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if constexpr (!SAFE) mask_row(r0 + 1 + k, c[k], e[k]);
             if (r0 + 1 + k > rows) {  // below the segment's last needed row
-                cn[k][0] = cn[k][1] = cn[k][2] = cn[k][3] = 0u;
-                en[k] = 0u;
+                c[k][0] = c[k][1] = c[k][2] = c[k][3] = 0u;
+                e[k] = 0u;
             }
             uint32_t hn[4], res[4];
-            hsum16(cn[k], lane_prev<S>(cn[k], en[k], sl), lane_next<S>(cn[k], en[k], sl), hn);
+            hsum16(c[k], lane_prev<S>(c[k], e[k], sl), lane_next<S>(c[k], e[k], sl), hn);
 #pragma unroll
             for (int i = 0; i < 4; ++i) res[i] = life_b3s23(hp[i] + hc[i] + hn[i], cc[i]);
             if (r0 + k < rows) store_row(r0 + k, res);
@@ -278,9 +278,18 @@ __device__ __forceinline__ void ca2_tile(const Plan &P, const uint8_t *__restric
             for (int i = 0; i < 4; ++i) {
                 hp[i] = hc[i];
                 hc[i] = hn[i];
-                cc[i] = cn[k][i];
+                cc[i] = c[k][i];
             }
         }
+    };
+    uint32_t cA[D][4], eA[D], cB[D][4], eB[D];
+    load_block(0, cA, eA);
+    for (int32_t r0 = 0; r0 < rows; r0 += 2 * D) {
+        if (r0 + D < rows) load_block(r0 + D, cB, eB);
+        sum_block(r0, cA, eA);
+        if (r0 + D >= rows) break;
+        if (r0 + 2 * D < rows) load_block(r0 + 2 * D, cA, eA);
+        sum_block(r0 + D, cB, eB);
     }
 }
 

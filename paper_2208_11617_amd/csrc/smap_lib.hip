@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -129,6 +131,19 @@ TileCfg tile_for(int m, int cls)
     return it != g_tiles.end() ? it->second : default_tile(m, cls);
 }
 
+// Autotuned H choices per (m, n, op class) (g_mu held when used).
+struct Tuned {
+    TileCfg t;
+    int beta;
+};
+std::map<std::tuple<int, int64_t, int>, Tuned> g_tuned;
+
+TileCfg tile_for_h(int m, int64_t n, int cls)
+{
+    auto it = g_tuned.find(std::make_tuple(m, n, cls));
+    return it != g_tuned.end() ? it->second.t : tile_for(m, cls);
+}
+
 int resolve_rb(int m, int r, int beta, int *beta_out)
 {
     if (r != 0 && r != 2) return kEunsupported;
@@ -198,7 +213,7 @@ int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C
 {
     const int cls = op_class(op);
     std::lock_guard<std::mutex> lk(g_mu);
-    const TileCfg t = tile_for(m, cls);
+    const TileCfg t = bb ? tile_for(m, cls) : tile_for_h(m, n, cls);
     *tc = t;
     return plan_for(m, n, beta, bb, cls, t, P, C);
 }
@@ -304,7 +319,10 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
         uint8_t *o8 = (uint8_t *)out;
-        constexpr int D = 2;  // rows in flight per wave (more costs occupancy)
+#ifndef SMAP_CA2_D
+#define SMAP_CA2_D 2
+#endif
+        constexpr int D = SMAP_CA2_D;  // rows per block; two blocks in flight per wave
         switch (tc.rho * 10000 + tc.wg) {
 #define SMAP_CA2(RHO, WG, W, R)                                                                  \
         case RHO * 10000 + WG:                                                                    \
@@ -355,6 +373,11 @@ int do_launch(int m, int64_t n, int r, int beta, int op, const void *in, void *o
     if (rc != kOk) return rc;
     int b = 0;
     if (!bb) {
+        if (beta == 0) {  // a tuned beta, if any
+            std::lock_guard<std::mutex> lk(g_mu);
+            auto it = g_tuned.find(std::make_tuple(m, n, op_class(op)));
+            if (it != g_tuned.end()) beta = it->second.beta;
+        }
         rc = resolve_rb(m, r, beta, &b);
         if (rc != kOk) return rc;
     }
@@ -517,6 +540,179 @@ int batch_launch(const simplex_job *jobs, int32_t njobs, void *stream)
     return kOk;
 }
 
+// ---- autotuning -----------------------------------------------------------
+
+// The compiled (rho, threads) choices of (m, op class).
+std::vector<TileCfg> tile_candidates(int m, int cls)
+{
+    std::vector<TileCfg> v;
+    if (cls == 0) {
+        for (const PointShape &c : kPointShapes)
+            if (c.m == m) v.push_back({c.rho, c.wg, c.sub});
+    } else if (cls == 1) {
+        for (const Ca2Shape &c : kCa2Shapes) v.push_back({c.rho, c.wg, c.sub});
+    } else {
+        for (const Ca3Shape &c : kCa3Shapes) v.push_back({c.rho, c.wg, c.sub});
+    }
+    return v;
+}
+
+bool device_key(char *buf, size_t len)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    char arch[64];
+    std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    for (char *c = arch; *c; ++c)
+        if (*c == ' ' || *c == ':') *c = '_';
+    std::snprintf(buf, len, "%s_%dcu", arch, prop.multiProcessorCount);
+    return true;
+}
+
+bool cache_lookup(const char *path, const char *dev, int m, int64_t n, int op, simplex_tune_result *r)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256], d[96];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        int mm, oo, rho, wg, beta;
+        long long nn;
+        float us;
+        if (std::sscanf(line, "smap-tune-v1 %95s %d %lld %d %d %d %d %f", d, &mm, &nn, &oo, &rho, &wg, &beta, &us) == 8 &&
+            std::strcmp(d, dev) == 0 && mm == m && nn == n && oo == op) {
+            *r = simplex_tune_result{rho, wg, beta, us};
+            found = true;  // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+int autotune(int m, int64_t n, int op, const void *in, void *out, int32_t reps, const char *cache_path,
+             void *stream, simplex_tune_result *best)
+{
+    if (!best || reps < 1) return kEinval;
+    int rc = check_op(m, n, op);
+    if (rc != kOk) return rc;
+    rc = check_buffers(m, n, op, in, out);
+    if (rc != kOk) return rc;
+    if (op == OP_ACCUM && in == out) return kEinval;
+    const int cls = op_class(op);
+    const auto key = std::make_tuple(m, n, cls);
+    char dev[96] = "unknown";
+    if (!device_key(dev, sizeof dev)) return kEhip;
+    simplex_tune_result r{};
+    if (cache_path && cache_lookup(cache_path, dev, m, n, op, &r)) {
+        int wg = r.wg_threads, sub = 1;
+        if (tile_supported(m, cls, r.rho, &wg, &sub)) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_tuned[key] = Tuned{{r.rho, wg, sub}, r.beta};
+            *best = r;
+            return kOk;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return kEhip;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return kEhip;
+    }
+    const std::vector<int> betas = m == 4 ? std::vector<int>{3, 4} : std::vector<int>{2};
+    simplex_tune_result top{0, 0, 0, 0.f};
+    bool have = false;
+    rc = kOk;
+    for (const TileCfg &t : tile_candidates(m, cls)) {
+        for (int beta : betas) {
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                g_tuned[key] = Tuned{t, beta};
+            }
+            int lr = kOk;
+            for (int i = 0; i < 2 && lr == kOk; ++i) lr = do_launch(m, n, 0, beta, op, in, out, stream, false);
+            if (lr == kErange) continue;  // this tile does not fit the index range
+            if (lr != kOk) { rc = lr; break; }
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = kEhip; break; }
+            for (int i = 0; i < reps && lr == kOk; ++i) lr = do_launch(m, n, 0, beta, op, in, out, stream, false);
+            if (lr != kOk) { rc = lr; break; }
+            float ms = 0.f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = kEhip; break; }
+            const float us = ms * 1e3f / (float)reps;
+            if (!have || us < top.us) top = simplex_tune_result{t.rho, t.wg, beta, us};
+            have = true;
+        }
+        if (rc != kOk) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (rc != kOk || !have) {
+        g_tuned.erase(key);
+        return rc != kOk ? rc : kErange;
+    }
+    int wg = top.wg_threads, sub = 1;
+    tile_supported(m, cls, top.rho, &wg, &sub);
+    g_tuned[key] = Tuned{{top.rho, wg, sub}, top.beta};
+    *best = top;
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "a");
+        if (!f) return kEinval;
+        std::fprintf(f, "smap-tune-v1 %s %d %lld %d %d %d %d %.3f\n", dev, m, (long long)n, op, top.rho,
+                     top.wg_threads, top.beta, top.us);
+        std::fclose(f);
+    }
+    return kOk;
+}
+
+// ---- graphs --------------------------------------------------------------
+
+struct GraphHandle {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int graph_create(int m, int64_t n, int r, int beta, int op, const void *in, void *out, int32_t steps,
+                 void **handle)
+{
+    if (!handle || steps < 1) return kEinval;
+    *handle = nullptr;
+    int rc = check_op(m, n, op);
+    if (rc != kOk) return rc;
+    rc = check_buffers(m, n, op, in, out);
+    if (rc != kOk) return rc;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return kEhip;
+    GraphHandle *h = new GraphHandle();
+    rc = kOk;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = kEhip;
+    } else {
+        const bool ca = op == OP_CA2 || op == OP_CA3;
+        for (int32_t i = 0; i < steps && rc == kOk; ++i) {
+            const void *a = (ca && (i & 1)) ? out : in;
+            void *b = (ca && (i & 1)) ? const_cast<void *>(in) : out;
+            rc = do_launch(m, n, r, beta, op, a, b, cs, false);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (rc == kOk && e != hipSuccess) rc = kEhip;
+        h->graph = g;
+        if (rc == kOk && hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) rc = kEhip;
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != kOk) {
+        if (h->exec) (void)hipGraphExecDestroy(h->exec);
+        if (h->graph) (void)hipGraphDestroy(h->graph);
+        delete h;
+        return rc;
+    }
+    *handle = h;
+    return kOk;
+}
+
 }  // namespace
 
 extern "C" {
@@ -663,8 +859,45 @@ int simplex_serve_run(const struct simplex_serve_job *jobs, int32_t njobs, void 
         local.resize((size_t)njobs);
         records = local.data();
     }
-    for (int32_t i = 0; i < njobs; ++i) records[i] = simplex_serve_record{-1.0, -1.0, -1.0, 0, -1, kOk};
+    for (int32_t i = 0; i < njobs; ++i) records[i] = simplex_serve_record{-1.0, -1.0, -1.0, -1.0, 0, -1, kOk};
     return serve_run(jobs, njobs, (uint8_t *)arena, arena_bytes, mode, max_inflight, keep_outputs, records);
+}
+
+int simplex_autotune(int m, int64_t n, int op, const void *buf_in, void *buf_out, int32_t reps,
+                     const char *cache_path, void *stream, struct simplex_tune_result *best)
+{
+    return autotune(m, n, op, buf_in, buf_out, reps, cache_path, stream, best);
+}
+
+int simplex_autotune_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned.clear();
+    return kOk;
+}
+
+int simplex_graph_create(int m, int64_t n, int r, int beta, int op, const void *buf_in, void *buf_out,
+                         int32_t steps, void **graph)
+{
+    return graph_create(m, n, r, beta, op, buf_in, buf_out, steps, graph);
+}
+
+int simplex_graph_launch(void *graph, void *stream)
+{
+    if (!graph) return kEinval;
+    GraphHandle *h = static_cast<GraphHandle *>(graph);
+    return hipGraphLaunch(h->exec, (hipStream_t)stream) == hipSuccess ? kOk : kEhip;
+}
+
+int simplex_graph_destroy(void *graph)
+{
+    if (!graph) return kOk;
+    GraphHandle *h = static_cast<GraphHandle *>(graph);
+    int rc = kOk;
+    if (h->exec && hipGraphExecDestroy(h->exec) != hipSuccess) rc = kEhip;
+    if (h->graph && hipGraphDestroy(h->graph) != hipSuccess) rc = kEhip;
+    delete h;
+    return rc;
 }
 
 const char *simplex_strerror(int status)

@@ -101,10 +101,13 @@ inline int serve_run(const simplex_serve_job *jobs, int32_t njobs, uint8_t *aren
         if (hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking) != hipSuccess) status = SMAP_EHIP;
     }
     if (status == SMAP_OK && hipEventCreate(&ev0) != hipSuccess) status = SMAP_EHIP;
+    // The run's clock starts at t0; the start event ev0 is placed at the
+    // midpoint of its record-and-wait on that clock.
+    const auto t0 = clock::now();
     if (status == SMAP_OK && hipEventRecord(ev0, streams[0]) != hipSuccess) status = SMAP_EHIP;
     if (status == SMAP_OK && hipEventSynchronize(ev0) != hipSuccess) status = SMAP_EHIP;
-    const auto t0 = clock::now();
     auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+    const double ev0_s = 0.5 * now_s();
 
     Arena heap(arena_bytes);
     std::deque<int32_t> waiting;    // arrived, not admitted
@@ -125,8 +128,10 @@ inline int serve_run(const simplex_serve_job *jobs, int32_t njobs, uint8_t *aren
                 if (q != hipSuccess) { status = SMAP_EHIP; break; }
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, ev0, f.ev) != hipSuccess) { status = SMAP_EHIP; break; }
+                const double seen = now_s();
                 for (int32_t j : f.jobs) {
-                    rec[j].done_s = ms * 1e-3;
+                    rec[j].done_s = ev0_s + ms * 1e-3;
+                    rec[j].release_s = seen;
                     if (!keep_outputs) heap.release(rec[j].out_offset, serve_box_bytes(jobs[j]));
                 }
                 done += (int32_t)f.jobs.size();
@@ -137,12 +142,12 @@ inline int serve_run(const simplex_serve_job *jobs, int32_t njobs, uint8_t *aren
             }
         }
         if (status != SMAP_OK) break;
-        // admission in arrival order
+        // admission in arrival order (after this pass's releases)
         while (!waiting.empty()) {
             const int32_t j = waiting.front();
             uint64_t off = 0;
             if (!heap.alloc(serve_box_bytes(jobs[j]), &off)) break;
-            rec[j].admit_s = now;
+            rec[j].admit_s = now_s();
             rec[j].out_offset = off;
             admitted.push_back(j);
             waiting.pop_front();

@@ -49,6 +49,36 @@ WORKLOADS = {
     "c4": dict(m=4, n=128, op="hash", seed=22081161704, dist=None, p=None),
 }
 
+# Serving stream: one automaton step per job, mixed sizes, Poisson arrivals.
+SERVE = dict(seed=22081161705, frac_m2=0.6, n2=(64, 4096), n3=(32, 512), p=0.25, levels=64)
+
+
+def serve_trace(count: int, rate_per_s=None, seed: int = SERVE["seed"], levels: int = SERVE["levels"]):
+    """Job stream [(m, n, arrival_s)]: a fraction frac_m2 of jobs with m = 2
+    and n log-uniform in n2, the rest m = 3 with n log-uniform in n3; each n
+    is rounded to one of ``levels`` log-spaced sizes of its class, so jobs of
+    one size can share an input box.  Arrivals are a Poisson process of rate
+    ``rate_per_s`` (None or 0: every job arrives at t = 0)."""
+    rng = np.random.default_rng(seed)
+    grids = {2: np.unique(np.round(np.geomspace(*SERVE["n2"], levels)).astype(np.int64)),
+             3: np.unique(np.round(np.geomspace(*SERVE["n3"], levels)).astype(np.int64))}
+    jobs, t = [], 0.0
+    for _ in range(count):
+        m = 2 if rng.random() < SERVE["frac_m2"] else 3
+        lo, hi = SERVE["n2"] if m == 2 else SERVE["n3"]
+        want = np.exp(rng.uniform(np.log(lo), np.log(hi)))
+        g = grids[m]
+        n = int(g[np.argmin(np.abs(np.log(g) - np.log(want)))])
+        if rate_per_s:
+            t += rng.exponential(1.0 / rate_per_s)
+        jobs.append((m, n, t))
+    return jobs
+
+
+def serve_seed(m: int, n: int) -> int:
+    """Seed of the shared input box of the jobs of size (m, n)."""
+    return SERVE["seed"] * 1000003 + m * 100000 + n
+
 
 def bern_threshold(p: float) -> int:
     """floor(p * 2^32), the comparison threshold on the top 32 bits."""

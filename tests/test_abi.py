@@ -160,3 +160,22 @@ def test_serve_run_argument_errors():
     # keep_outputs needs room for every output at once
     two = [(2, "ca2", 730, 4096, 0.0), (2, "ca2", 730, 4096, 0.0)]
     assert smap.serve_run_raw(two, arena, size, smap.SERVE_BATCHED, 2, True)[0] == E
+
+
+def test_autotune_and_graph_argument_errors():
+    """Validation happens before any device work."""
+    import ctypes
+    E = smap.EINVAL
+    assert smap.autotune_raw(2, 100, "accum", 4096, 1 << 20, reps=0)[0] == E
+    assert smap.autotune_raw(2, 100, "ca3", 4096, 1 << 20)[0] == E          # CA3 needs m = 3
+    assert smap.autotune_raw(2, 100, "accum", 4096, 4096)[0] == E            # no in-place timing
+    assert smap.autotune_raw(2, -1, "accum", 4096, 1 << 20)[0] == E
+    assert smap.lib().simplex_autotune(2, 100, 1, 4096, 1 << 20, 5, None, None, None) == E
+    assert smap.autotune_reset() is None
+    L = smap.lib()
+    h = ctypes.c_void_p()
+    assert L.simplex_graph_create(2, 100, 0, 0, 1, 4096, 1 << 20, 0, ctypes.byref(h)) == E   # steps < 1
+    assert L.simplex_graph_create(2, 100, 0, 0, 1, 4096, 1 << 20, 2, None) == E              # no handle
+    assert L.simplex_graph_create(3, 100, 0, 0, 4, 4096, 1 << 20, 2, ctypes.byref(h)) == E   # CA2 with m = 3
+    assert L.simplex_graph_launch(None, None) == E
+    assert L.simplex_graph_destroy(None) == smap.OK

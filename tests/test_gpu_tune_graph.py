@@ -1,0 +1,114 @@
+"""Autotuning and HIP graphs on the GPU.
+
+The tuned launch must give the same result as the oracle (the choice of
+tile, workgroup size and beta never changes a result), the disk cache must
+return the stored choice, and every replay of a captured graph must equal
+the same launches run eagerly, with eager work between the replays.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import simplex_inputs as si
+from oracle import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def smap():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_11617_amd import binding
+    binding.lib()
+    yield binding
+    binding.autotune_reset()
+
+
+def expected(m, n, op, inp):
+    out = si.sentinel_box(m, n, oracle.dtype_of(op))
+    oracle.apply(m, n, op, inp, out)
+    return out
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32 if a.dtype == np.uint32 else np.uint8)).cuda()
+
+
+@pytest.mark.parametrize("m,n,op", [(2, 300, "accum"), (3, 45, "hash"), (4, 33, "hash"),
+                                    (2, 700, "ca2"), (3, 70, "ca3")])
+def test_autotune_result_and_cache(smap, tmp_path, m, n, op):
+    dist = {"accum": "u31", "ca2": "bern", "ca3": "bern"}.get(op)
+    inp = si.box(m, n, dist, 7000 + n, p=0.3) if dist else None
+    want = expected(m, n, op, inp)
+    d_in = dev(inp) if inp is not None else None
+    d_out = dev(si.sentinel_box(m, n, want.dtype))
+    cache = str(tmp_path / "tune.txt")
+    say(f"autotune m={m} n={n} {op}")
+    best = smap.autotune(m, n, op, d_in, d_out, reps=5, cache_path=cache)
+    torch.cuda.synchronize()
+    assert best["us"] > 0 and best["rho"] > 0
+    assert best["beta"] in ((3, 4) if m == 4 else (2,))
+    assert np.array_equal(d_out.cpu().numpy().view(want.dtype), want)
+    # a fresh launch with the tuned choice (beta 0 = the tuned beta)
+    d_out2 = dev(si.sentinel_box(m, n, want.dtype))
+    smap.map_launch(m, n, op, d_in, d_out2)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_out2.cpu().numpy().view(want.dtype), want)
+    assert os.path.exists(cache) and "smap-tune-v1" in open(cache).read()
+    # the cache returns the stored choice without timing
+    smap.autotune_reset()
+    again = smap.autotune(m, n, op, d_in, d_out, reps=5, cache_path=cache)
+    assert (again["rho"], again["wg_threads"], again["beta"]) == (best["rho"], best["wg_threads"], best["beta"])
+    assert abs(again["us"] - best["us"]) < 1e-2
+
+
+def test_graph_accum_in_place_replays(smap):
+    m, n, steps = 2, 500, 3
+    inp = si.box(m, n, "u31", 7100, poison=True)
+    buf = dev(inp)
+    other = dev(si.box(m, n, "u31", 7101))
+    other_want = dev(expected(m, n, "accum", si.box(m, n, "u31", 7101)))
+    g = smap.Graph(m, n, "accum", buf, buf, steps=steps)
+    inside = torch.from_numpy(si.inside_mask(m, n)).cuda()
+    base = buf.clone()
+    try:
+        for k in range(1, 5):
+            say(f"graph replay {k}")
+            g.launch()
+            torch.cuda.synchronize()
+            want = torch.where(inside, base + steps * k, base)   # int32 wraps like uint32
+            assert torch.equal(buf, want), k
+            # eager work between the replays
+            tmp = torch.full_like(other, 0)
+            smap.map_launch(m, n, "accum", other, tmp)
+            torch.cuda.synchronize()
+            assert torch.equal(torch.where(inside, tmp, other_want), other_want)
+    finally:
+        g.close()
+
+
+def test_graph_ca2_ping_pong_replays(smap):
+    m, n, steps = 2, 777, 4
+    inp = si.box(m, n, "bern", 7200, p=0.3)
+    a, b = dev(inp), dev(si.sentinel_box(m, n, np.uint8))
+    ea, eb = a.clone(), b.clone()
+    g = smap.Graph(m, n, "ca2", a, b, steps=steps)
+    try:
+        for k in range(3):
+            say(f"ca2 graph replay {k}")
+            g.launch()
+            for i in range(steps):          # the same steps, eagerly, on copies
+                src, dst = (ea, eb) if i % 2 == 0 else (eb, ea)
+                smap.map_launch(m, n, "ca2", src, dst)
+            torch.cuda.synchronize()
+            assert torch.equal(a, ea) and torch.equal(b, eb), k
+    finally:
+        g.close()
