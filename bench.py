@@ -288,18 +288,25 @@ def main():
         K = args.graph if not u8 else args.graph + (args.graph % 2)
         src = bufs[0] if bufs else None
         dst = None if op == "map" else out_a
-        g = smap.Graph(m, n, op, src, dst, steps=K, beta=args.beta)
         reps = max(1, args.steps // K)
+
+        def graph_ms(use_bb):
+            g = smap.Graph(m, n, op, src, dst, steps=K, beta=args.beta, use_bb=use_bb)
+            ms = time_launches(lambda i: g.launch(stream), reps, max(1, args.warmup // K), stream) / K
+            g.close()
+            return ms
         log(f"timing H as graph replays: {reps} x {K} launches")
-        h_ms = time_launches(lambda i: g.launch(stream), reps, max(1, args.warmup // K), stream) / K
-        g.close()
+        h_ms = graph_ms(False)
     else:
         log(f"timing H: {args.warmup} warmup + {args.steps} steps")
         h_ms = time_launches(step_fn(h_launch), args.steps, args.warmup, stream)
     bb_ms = None
     if not args.no_bb:
-        log("timing BB")
-        bb_ms = time_launches(step_fn(smap.bb_launch), args.steps, args.warmup, stream)
+        log("timing BB" + (" as graph replays" if args.graph > 0 else ""))
+        if args.graph > 0:
+            bb_ms = graph_ms(True)
+        else:
+            bb_ms = time_launches(step_fn(smap.bb_launch), args.steps, args.warmup, stream)
 
     copy = None
     if not args.no_copy:

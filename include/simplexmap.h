@@ -202,7 +202,8 @@ int simplex_autotune(int m, int64_t n, int op, const void *buf_in, void *buf_out
 int simplex_autotune_reset(void);
 
 /*
- * Captures `steps` H launches of op over (m, n) into a HIP graph (an
+ * Captures `steps` launches of op over (m, n) -- H, or BB when use_bb is
+ * non-zero (r and beta are then ignored) -- into a HIP graph (an
  * executable graph instance, *graph).  Pointwise ops repeat the same launch
  * (ACCUM in place adds `steps` per replay); the automata alternate
  * buf_in -> buf_out, buf_out -> buf_in, ... (an even `steps` leaves the
@@ -211,8 +212,8 @@ int simplex_autotune_reset(void);
  * recorded.  Errors as for simplex_map_launch; steps < 1 or a NULL graph
  * gives SMAP_EINVAL; a capture or instantiation failure gives SMAP_EHIP.
  */
-int simplex_graph_create(int m, int64_t n, int r, int beta, int op, const void *buf_in, void *buf_out,
-                         int32_t steps, void **graph);
+int simplex_graph_create(int m, int64_t n, int r, int beta, int op, int use_bb, const void *buf_in,
+                         void *buf_out, int32_t steps, void **graph);
 
 /* Enqueues one replay of the graph on `stream`. */
 int simplex_graph_launch(void *graph, void *stream);

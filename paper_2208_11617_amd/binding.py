@@ -122,7 +122,7 @@ def lib():
     L.simplex_autotune.restype = ci
     L.simplex_autotune_reset.argtypes = []
     L.simplex_autotune_reset.restype = ci
-    L.simplex_graph_create.argtypes = [ci, i64, ci, ci, ci, vp, vp, ctypes.c_int32, ctypes.POINTER(vp)]
+    L.simplex_graph_create.argtypes = [ci, i64, ci, ci, ci, ci, vp, vp, ctypes.c_int32, ctypes.POINTER(vp)]
     L.simplex_graph_create.restype = ci
     L.simplex_graph_launch.argtypes = [vp, vp]
     L.simplex_graph_launch.restype = ci
@@ -277,12 +277,12 @@ def autotune_reset() -> None:
 
 
 class Graph:
-    """A captured run of `steps` H launches (simplex_graph_create)."""
+    """A captured run of `steps` H (or BB) launches (simplex_graph_create)."""
 
-    def __init__(self, m, n, op, buf_in=None, buf_out=None, steps=1, r=0, beta=0):
+    def __init__(self, m, n, op, buf_in=None, buf_out=None, steps=1, r=0, beta=0, use_bb=False):
         h = ctypes.c_void_p()
-        _check(lib().simplex_graph_create(m, n, r, beta, _op(op), _ptr(buf_in), _ptr(buf_out), steps,
-                                          ctypes.byref(h)), "simplex_graph_create")
+        _check(lib().simplex_graph_create(m, n, r, beta, _op(op), 1 if use_bb else 0, _ptr(buf_in),
+                                          _ptr(buf_out), steps, ctypes.byref(h)), "simplex_graph_create")
         self.handle = h
 
     def launch(self, stream=None) -> None:

@@ -77,7 +77,11 @@ __device__ __forceinline__ void st_masked(uint8_t *row, int32_t x, int32_t r, in
     if (v >= 4) {
         st_u32(row + x, val);
     } else {
-        for (int k = 0; k < v; ++k) row[x + k] = (uint8_t)(val >> (8 * k));
+        // at most 3 bytes; unrolled (no loop), so every path issues a bounded
+        // number of stores and the wait counts before later loads stay exact
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k < v) row[x + k] = (uint8_t)(val >> (8 * k));
     }
 }
 
@@ -175,26 +179,29 @@ __device__ __forceinline__ void ca2_tile(const Plan &P, const uint8_t *__restric
     // and neither does the 4-byte halo access; the host launches the SAFE
     // instantiation (byte-safe loads through ld_masked) for smaller n.
 
-    // Raw loads of wave row r: the lane's 16 cells (if any is in the
-    // simplex) and its halo dword (first/last lane of a segment).  No masking
-    // here, so the loads of a block issue back to back.
+    // Raw loads of wave row r: the lane's 16 cells and its halo dword (first
+    // and last lane of a segment).  No masking here, so the loads of a block
+    // issue back to back.  The 16-byte load is issued by every lane, reading
+    // the buffer's first 16 bytes when the lane has no simplex cell in the
+    // row (mask_row clears it): unconditional loads keep the number of loads
+    // issued after a row known, so the wait before the row's use covers that
+    // row only and the loads of the next block stay in flight.  The halo load
+    // (few lanes) is conditional and issued first.
     auto load_raw = [&](int32_t r, uint32_t *c, uint32_t &e) {
-        c[0] = c[1] = c[2] = c[3] = 0u;
-        e = 0u;
         const int32_t y = ywave + r + lane_rows;
-        if ((uint32_t)y > (uint32_t)n) return;      // y < 0 or y > n
+        const bool yin = (uint32_t)y <= (uint32_t)n;   // 0 <= y <= n
         const uint8_t *rowp = in + (int64_t)(ywave + r) * pitch;   // wave-uniform
-        if (x <= n - y) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(rowp + off_c);
-            c[0] = q.x; c[1] = q.y; c[2] = q.z; c[3] = q.w;
-        }
-        if (is_edge && xe >= 0 && xe <= n - y) e = ld_u32(rowp + off_e);
+        e = 0u;
+        if (is_edge && yin && xe >= 0 && xe <= n - y) e = ld_u32(rowp + off_e);
+        const bool has = yin && x <= n - y;
+        const uint4 q = *reinterpret_cast<const uint4 *>(has ? rowp + off_c : in);
+        c[0] = q.x; c[1] = q.y; c[2] = q.z; c[3] = q.w;
     };
     // Zero the cells of wave row r that lie outside the simplex (only the
     // lane the hypotenuse cuts, and the right halo byte, can hold any).
     auto mask_row = [&](int32_t r, uint32_t *c, uint32_t &e) {
         const int32_t y = ywave + r + lane_rows;
-        const int32_t v = n - y - x + 1;             // simplex cells from x on
+        const int32_t v = y < 0 ? 0 : n - y - x + 1;  // simplex cells from x on
         if (v < 16) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -282,13 +289,14 @@ __device__ __forceinline__ void ca2_tile(const Plan &P, const uint8_t *__restric
             }
         }
     };
+    // Both halves of the unrolled loop always run (rows past the segment's
+    // last are cleared and not stored), so every block issues its loads.
     uint32_t cA[D][4], eA[D], cB[D][4], eB[D];
     load_block(0, cA, eA);
     for (int32_t r0 = 0; r0 < rows; r0 += 2 * D) {
-        if (r0 + D < rows) load_block(r0 + D, cB, eB);
+        load_block(r0 + D, cB, eB);
         sum_block(r0, cA, eA);
-        if (r0 + D >= rows) break;
-        if (r0 + 2 * D < rows) load_block(r0 + 2 * D, cA, eA);
+        load_block(r0 + 2 * D, cA, eA);
         sum_block(r0 + D, cB, eB);
     }
 }

@@ -99,29 +99,42 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
         off = (uint32_t)max(y, 0) * (uint32_t)p1 + (uint32_t)max(xs, 0);
     };
     // Raw loads of the lane's chunks of plane z (no masking: the loads of a
-    // plane issue back to back).  Chunks that hold no simplex cell, and
-    // planes outside 0..n, are not loaded.
+    // plane issue back to back).  Outside the byte-safe instantiation every
+    // lane issues all KQ loads, reading the buffer's first 16 bytes for a
+    // chunk with no simplex cell (or a plane outside 0..n); commit_plane
+    // clears such chunks.  Unconditional loads keep the number of loads
+    // issued after a register set known, so the wait before its use is a
+    // partial one and the loads of the next planes stay in flight.
     auto load_plane = [&](int32_t z, uint4 (&R)[KQ]) {
+        const bool zin = (uint32_t)z <= (uint32_t)n;   // uniform
+        if constexpr (SAFE) {
 #pragma unroll
-        for (int k = 0; k < KQ; ++k) R[k] = make_uint4(0u, 0u, 0u, 0u);
-        if ((uint32_t)z > (uint32_t)n) return;    // uniform
-        const uint8_t *pl = in + (int64_t)z * p2;
+            for (int k = 0; k < KQ; ++k) R[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (!zin) return;
 #pragma unroll
-        for (int k = 0; k < KQ; ++k) {
-            if (NCH % NT != 0 && tid + k * NT >= NCH) continue;
-            int32_t y, xs;
-            uint32_t off;
-            chunk_geom(k, y, xs, off);
-            const int32_t xl = max(xs, 0);
-            if (y < 0 || n - z - y - xl < 0) continue;   // first loaded cell outside
-            if constexpr (SAFE) {
+            for (int k = 0; k < KQ; ++k) {
+                if (NCH % NT != 0 && tid + k * NT >= NCH) continue;
+                int32_t y, xs;
+                uint32_t off;
+                chunk_geom(k, y, xs, off);
+                const int32_t xl = max(xs, 0);
+                if (y < 0 || n - z - y - xl < 0) continue;
                 const int64_t rb = (int64_t)z * p2 + (int64_t)y * p1;
                 R[k].x = ld_masked(in + rb, xl, y + z, n, total - rb);
                 R[k].y = ld_masked(in + rb, xl + 4, y + z, n, total - rb);
                 R[k].z = ld_masked(in + rb, xl + 8, y + z, n, total - rb);
                 R[k].w = ld_masked(in + rb, xl + 12, y + z, n, total - rb);
-            } else {
-                R[k] = *reinterpret_cast<const uint4 *>(pl + off);
+            }
+        } else {
+            const uint8_t *pl = in + (int64_t)(zin ? z : 0) * p2;   // uniform
+#pragma unroll
+            for (int k = 0; k < KQ; ++k) {
+                int32_t y, xs;
+                uint32_t off;
+                chunk_geom(k, y, xs, off);
+                const bool has = zin && (NCH % NT == 0 || tid + k * NT < NCH) && y >= 0 &&
+                                 n - z - y - max(xs, 0) >= 0;
+                R[k] = *reinterpret_cast<const uint4 *>(has ? pl + off : in);
             }
         }
     };
@@ -193,12 +206,17 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
     __syncthreads();
 
     uint32_t sp[RL][4] = {}, sc[RL][4] = {}, cp[RL][4] = {};
-    const int32_t steps = nz + 2;                 // staged planes z0-1 .. z0+nz
+    // Staged planes z0-1 .. z0+nz; the walk runs an even number of steps so
+    // that both halves of the unrolled loop always run (a step beyond the
+    // last plane stages zeros or unused cells and stores nothing), and every
+    // step issues its loads: the wait before a register set's use then only
+    // covers that set, not the loads issued after it.
+    const int32_t steps = (nz + 3) & ~1;
     // Step i: plane z0-1+i is staged in lds[i & 1] and RX holds plane z0+i.
     auto step = [&](int32_t i, uint4 (&RX)[KQ]) {
         uint32_t sn[RL][4], cn[RL][4];
         plane_sums(i & 1, sn, cn);
-        if (i >= 2) {                             // output plane z0 + i - 2
+        if (i >= 2 && i < nz + 2) {               // output plane z0 + i - 2
             const int32_t z = z0 + i - 2;
 #pragma unroll
             for (int j = 0; j < RL; ++j) {
@@ -227,15 +245,13 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
                 cp[j][k] = cn[j][k];
             }
         }
-        if (i + 1 < steps) {
-            commit_plane(z0 + i, RX, (i + 1) & 1);        // staged for step i + 1
-            if (i + 3 < steps) load_plane(z0 + i + 2, RX);   // consumed at step i + 2
-        }
+        commit_plane(z0 + i, RX, (i + 1) & 1);   // staged for step i + 1
+        load_plane(z0 + i + 2, RX);               // consumed at step i + 2
         __syncthreads();
     };
     for (int32_t i = 0; i < steps; i += 2) {
         step(i, RA);
-        if (i + 1 < steps) step(i + 1, RB);
+        step(i + 1, RB);
     }
 }
 

@@ -66,6 +66,31 @@ namespace smap {
 
 constexpr int kMaxLevels = 16;
 
+// Division by a workgroup-uniform divisor d >= 1 through a multiplier
+// computed once on the host (Granlund and Montgomery, "Division by
+// invariant integers using multiplication", PLDI 1994, the unsigned
+// round-up method for 32-bit words): exact for every 32-bit x.  On the GPU
+// it is a scalar multiply-high, a subtract, an add and two shifts.
+struct Divu {
+    uint32_t d, m, sh1, sh2;
+};
+
+SMAP_HD Divu make_divu(uint32_t d)
+{
+    uint32_t l = 0;  // ceil(log2 d)
+    while ((uint64_t(1) << l) < (uint64_t)d) ++l;
+    const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1u;
+    return Divu{d, (uint32_t)m, l < 1u ? l : 1u, l > 1u ? l - 1u : 0u};
+}
+
+SMAP_HD uint32_t divu(uint32_t x, uint32_t m, uint32_t sh1, uint32_t sh2)
+{
+    const uint32_t t1 = (uint32_t)(((uint64_t)m * x) >> 32);
+    return (t1 + ((x - t1) >> sh1)) >> sh2;
+}
+
+SMAP_HD uint32_t divu(uint32_t x, const Divu &D) { return divu(x, D.m, D.sh1, D.sh2); }
+
 // Everything a kernel needs to decode its workgroup id.  Passed by value in
 // the kernel arguments (it ends up in scalar registers / the constant cache).
 struct Plan {
@@ -84,7 +109,11 @@ struct Plan {
     uint32_t base_count[4];      // workgroups of the base map of each piece
     uint32_t lvl_start[kMaxLevels + 1];
     int64_t stride[4];           // element strides (n+1)^k
+    Divu base_div[4];            // division by base_count[p]
+    Divu L_div;                  // division by L (1 when there is no shell)
+    Divu kbox_div;               // division by kbox (BB, m = 4)
     uint32_t grid[3];            // launch grid of this launch (set per launch)
+    Divu grid_div[2];            // division by grid[0], grid[1] (set per launch)
     uint32_t nwg;                // grid[0] * grid[1] * grid[2] (< 2^32)
     uint32_t remap;              // 1: renumber workgroups with xcd_remap
 };
@@ -112,10 +141,11 @@ __device__ __forceinline__ WgId wg_id(const Plan &P)
 {
 #ifndef SMAP_NO_XCD_REMAP
     if (P.remap) {
+        if (P.grid[1] == 1 && P.grid[2] == 1) return {xcd_remap(blockIdx.x, P.nwg), 0u, 0u};  // 1-D: no division
         const uint32_t L = (blockIdx.z * P.grid[1] + blockIdx.y) * P.grid[0] + blockIdx.x;
         const uint32_t g = xcd_remap(L, P.nwg);
-        const uint32_t gx = g % P.grid[0], r = g / P.grid[0];
-        return {gx, r % P.grid[1], r / P.grid[1]};
+        const uint32_t r = divu(g, P.grid_div[0]), r2 = divu(r, P.grid_div[1]);
+        return {g - r * P.grid[0], r - r2 * P.grid[1], r2};
     }
 #endif
     return {blockIdx.x, blockIdx.y, blockIdx.z};
@@ -212,10 +242,11 @@ SMAP_HD bool h4_native(const Plan &P, uint32_t w, int32_t *t)
     int32_t lam[4], o[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) lam[k] = (int32_t)((cell >> (uint32_t(k) * lc)) & (c - 1u));
-    const uint32_t beta = (uint32_t)P.beta;
+    const bool b4 = P.beta == 4;                  // beta is 3 or 4: constant divisors
     for (int k = l; k >= 1; --k) {                // corner chosen at depth k
-        const uint32_t d = q % beta;
-        q /= beta;
+        const uint32_t q3 = q / 3u;
+        const uint32_t d = b4 ? (q & 3u) : q - 3u * q3;
+        q = b4 ? (q >> 2) : q3;
         const int32_t step = (int32_t)((1u << P.j) >> k);
         // select the axis without a dynamically indexed array (no scratch)
         o[0] += d == 0u ? step : 0;
@@ -244,15 +275,20 @@ SMAP_HD bool decode_h(const Plan &P, uint32_t w, int32_t *t)
 {
     constexpr int m = M;
     // piece: last p with piece_start[p] <= w (unrolled: no runtime-indexed reads)
+    // (scalar fields selected one by one: a selected struct or array element
+    // would be turned into a runtime-indexed local copy in scratch memory)
     int p = 0;
     uint32_t pstart = 0, bc = P.base_count[0];
+    uint32_t bm = P.base_div[0].m, bs1 = P.base_div[0].sh1, bs2 = P.base_div[0].sh2;
 #pragma unroll
     for (int k = 1; k < M; ++k) {
-        if (k < P.npieces && w >= P.piece_start[k]) {
-            p = k;
-            pstart = P.piece_start[k];
-            bc = P.base_count[k];
-        }
+        const bool in_k = k < P.npieces && w >= P.piece_start[k];
+        p = in_k ? k : p;
+        pstart = in_k ? P.piece_start[k] : pstart;
+        bc = in_k ? P.base_count[k] : bc;
+        bm = in_k ? P.base_div[k].m : bm;
+        bs1 = in_k ? P.base_div[k].sh1 : bs1;
+        bs2 = in_k ? P.base_div[k].sh2 : bs2;
     }
     const uint32_t loc = w - pstart;
     if (p == 0) {
@@ -261,8 +297,8 @@ SMAP_HD bool decode_h(const Plan &P, uint32_t w, int32_t *t)
         else return h4_native(P, loc, t);
     }
     const int d = m - p;                          // base dimension of this piece
-    const uint32_t base = loc % bc;
-    uint32_t lay = loc / bc;
+    uint32_t lay = divu(loc, bm, bs1, bs2);
+    const uint32_t base = loc - lay * bc;
     if (d == 1) {
         t[0] = (int32_t)base;
     } else if (d == 2) {
@@ -281,8 +317,9 @@ SMAP_HD bool decode_h(const Plan &P, uint32_t w, int32_t *t)
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
         if (k >= d && k < m) {
-            const int32_t ik = (int32_t)(lay % L);
-            lay /= L;
+            const uint32_t next = divu(lay, P.L_div);
+            const int32_t ik = (int32_t)(lay - next * L);
+            lay = next;
             t[k] = h + ik - s;
             ok = ok && t[k] >= 0;
             s = h + ik;
@@ -306,8 +343,9 @@ SMAP_HD void decode_bb(const Plan &P, uint32_t gx, uint32_t gy, uint32_t gz, int
     t[1] = (int32_t)gy;
     if (P.m == 3) t[2] = (int32_t)gz;
     if (P.m == 4) {
-        t[2] = (int32_t)(gz % (uint32_t)P.kbox);
-        t[3] = (int32_t)(gz / (uint32_t)P.kbox);
+        const uint32_t q = divu(gz, P.kbox_div);
+        t[2] = (int32_t)(gz - q * (uint32_t)P.kbox);
+        t[3] = (int32_t)q;
     }
 }
 

@@ -53,7 +53,7 @@ constexpr PointShape kPointShapes[] = {
 
 // CA3 shapes: (rho, threads) -> rows RY (y), planes RZ (z), rows per lane RL.
 #ifndef SMAP_CA3_RZ
-#define SMAP_CA3_RZ 32
+#define SMAP_CA3_RZ 16
 #endif
 struct Ca3Shape {
     int rho, wg, ry, rz, rl, sub;
@@ -309,13 +309,17 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
     PL.grid[1] = grid.y;
     PL.grid[2] = grid.z;
     PL.nwg = grid.x * grid.y * grid.z;
+    PL.grid_div[0] = make_divu(grid.x);
+    PL.grid_div[1] = make_divu(grid.y);
     // H runs XCD-contiguous (its workgroups are nearly all useful, so every
-    // XCD gets an equal share of the work).  BB keeps the hardware order: a
-    // contiguous split would hand the XCDs at the end of the range mostly
-    // empty box tiles.  The 3-D automaton also keeps the hardware order
-    // (measured faster: its sub-major order already spreads the concurrent
+    // XCD gets an equal share of the work) when neighbouring tiles share
+    // cache lines: the pointwise ops that touch memory and the 2-D
+    // automaton.  BB keeps the hardware order: a contiguous split would hand
+    // the XCDs at the end of the range mostly empty box tiles.  Measured
+    // faster in the hardware order: MAP (no memory traffic to share) and the
+    // 3-D automaton (its sub-major order already spreads the concurrent
     // workgroups over the buffer).
-    PL.remap = (BB || op == OP_CA3) ? 0u : 1u;
+    PL.remap = (BB || op == OP_CA3 || op == OP_MAP) ? 0u : 1u;
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
         uint8_t *o8 = (uint8_t *)out;
@@ -674,8 +678,8 @@ struct GraphHandle {
     hipGraphExec_t exec = nullptr;
 };
 
-int graph_create(int m, int64_t n, int r, int beta, int op, const void *in, void *out, int32_t steps,
-                 void **handle)
+int graph_create(int m, int64_t n, int r, int beta, int op, bool bb, const void *in, void *out,
+                 int32_t steps, void **handle)
 {
     if (!handle || steps < 1) return kEinval;
     *handle = nullptr;
@@ -694,7 +698,7 @@ int graph_create(int m, int64_t n, int r, int beta, int op, const void *in, void
         for (int32_t i = 0; i < steps && rc == kOk; ++i) {
             const void *a = (ca && (i & 1)) ? out : in;
             void *b = (ca && (i & 1)) ? const_cast<void *>(in) : out;
-            rc = do_launch(m, n, r, beta, op, a, b, cs, false);
+            rc = do_launch(m, n, r, beta, op, a, b, cs, bb);
         }
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(cs, &g);
@@ -876,10 +880,10 @@ int simplex_autotune_reset(void)
     return kOk;
 }
 
-int simplex_graph_create(int m, int64_t n, int r, int beta, int op, const void *buf_in, void *buf_out,
-                         int32_t steps, void **graph)
+int simplex_graph_create(int m, int64_t n, int r, int beta, int op, int use_bb, const void *buf_in,
+                         void *buf_out, int32_t steps, void **graph)
 {
-    return graph_create(m, n, r, beta, op, buf_in, buf_out, steps, graph);
+    return graph_create(m, n, r, beta, op, use_bb != 0, buf_in, buf_out, steps, graph);
 }
 
 int simplex_graph_launch(void *graph, void *stream)

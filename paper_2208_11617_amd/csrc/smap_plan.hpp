@@ -84,6 +84,7 @@ inline int make_plan(int m, int64_t n, int beta, int rho, bool bb, Plan *P, Plan
     if (bb) {
         const int64_t kb = (n + 1 + rho - 1) / rho;
         P->kbox = (int32_t)kb;
+        P->kbox_div = make_divu((uint32_t)kb);
         // hardware grid limits: y and z (z = kbox^2 for m = 4) below 65536
         if (kb > 65535 || (m == 4 && kb * kb > 65535)) return kErange;
         uint64_t tot = 1;
@@ -125,6 +126,8 @@ inline int make_plan(int m, int64_t n, int beta, int rho, bool bb, Plan *P, Plan
         if (acc > kMaxWorkgroups) return kErange;
         P->piece_start[P->npieces] = (uint32_t)acc;
         P->total = (uint32_t)acc;
+        for (int p = 0; p < P->npieces; ++p) P->base_div[p] = make_divu(P->base_count[p] ? P->base_count[p] : 1u);
+        P->L_div = make_divu(P->L > 0 ? (uint32_t)P->L : 1u);
         cnt.launched = acc;
     }
     if (C) *C = cnt;

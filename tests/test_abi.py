@@ -174,8 +174,8 @@ def test_autotune_and_graph_argument_errors():
     assert smap.autotune_reset() is None
     L = smap.lib()
     h = ctypes.c_void_p()
-    assert L.simplex_graph_create(2, 100, 0, 0, 1, 4096, 1 << 20, 0, ctypes.byref(h)) == E   # steps < 1
-    assert L.simplex_graph_create(2, 100, 0, 0, 1, 4096, 1 << 20, 2, None) == E              # no handle
-    assert L.simplex_graph_create(3, 100, 0, 0, 4, 4096, 1 << 20, 2, ctypes.byref(h)) == E   # CA2 with m = 3
+    assert L.simplex_graph_create(2, 100, 0, 0, 1, 0, 4096, 1 << 20, 0, ctypes.byref(h)) == E   # steps < 1
+    assert L.simplex_graph_create(2, 100, 0, 0, 1, 0, 4096, 1 << 20, 2, None) == E              # no handle
+    assert L.simplex_graph_create(3, 100, 0, 0, 4, 1, 4096, 1 << 20, 2, ctypes.byref(h)) == E   # CA2 with m = 3
     assert L.simplex_graph_launch(None, None) == E
     assert L.simplex_graph_destroy(None) == smap.OK

@@ -95,12 +95,13 @@ def test_graph_accum_in_place_replays(smap):
         g.close()
 
 
-def test_graph_ca2_ping_pong_replays(smap):
+@pytest.mark.parametrize("use_bb", [False, True])
+def test_graph_ca2_ping_pong_replays(smap, use_bb):
     m, n, steps = 2, 777, 4
     inp = si.box(m, n, "bern", 7200, p=0.3)
     a, b = dev(inp), dev(si.sentinel_box(m, n, np.uint8))
     ea, eb = a.clone(), b.clone()
-    g = smap.Graph(m, n, "ca2", a, b, steps=steps)
+    g = smap.Graph(m, n, "ca2", a, b, steps=steps, use_bb=use_bb)
     try:
         for k in range(3):
             say(f"ca2 graph replay {k}")
