@@ -215,7 +215,7 @@ def main():
     ap.add_argument("--jobs", type=int, default=10000, help="c5: jobs in the stream")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="c5: output arena")
     ap.add_argument("--load", type=float, default=0.8, help="c5: offered load / sequential rate")
-    ap.add_argument("--max-inflight", type=int, default=2, help="c5: batches in flight")
+    ap.add_argument("--max-inflight", type=int, default=4, help="c5: batches in flight")
     ap.add_argument("--warmup-replays", type=int, default=1, help="c5: untimed replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-bb", action="store_true", help="skip timing the BB baseline")

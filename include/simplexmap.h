@@ -254,11 +254,13 @@ struct simplex_job {
  *
  * The table travels from pinned host memory to device memory with an
  * asynchronous copy on `stream`, then the launch follows on `stream`; the
- * call returns without synchronising.  The library keeps a small ring of
- * table buffers per device (allocated on the first call, kept until the
- * process ends) and waits, on the host, only when a ring slot is still in
- * use by an earlier batch.  Jobs of one class are launched together up to
- * 4096 per launch (more are split over several launches).
+ * call returns without synchronising.  Tables are cut from a 32 MiB byte
+ * ring per device (pinned host staging plus a device copy, allocated on
+ * the first call and kept until the process ends); a table's bytes are
+ * reused once the event recorded after its launch has completed, and the
+ * call waits on the host only when the ring is full.  Jobs of one class are
+ * launched together up to 4096 per launch (more are split over several
+ * launches).
  *
  * Errors: SMAP_EINVAL for njobs < 0, a NULL `jobs` with njobs > 0, a job
  * with an unsupported (m, op), a negative n, NULL or overlapping buffers;
@@ -316,7 +318,11 @@ struct simplex_serve_record {
  * jobs go out as one simplex_batch_launch.  Batches alternate between two
  * streams of the default priority (created and destroyed by the call), so
  * consecutive batches overlap on the device.  Jobs that arrive while
- * others run join the next batch.
+ * others run join the next batch.  Before the clock starts, one tiny step
+ * of each class runs on every stream of the loop (a kernel's first launch
+ * in a process otherwise pays for loading its code object), on 16 KiB of
+ * zeroed device memory the library keeps with its job tables (never on the
+ * arena or a job's buffers).
  *
  * records (may be NULL) receives one entry per job.  Errors: SMAP_EINVAL for
  * bad arguments (including a job that could never fit the arena),

@@ -233,7 +233,7 @@ def batch_launch(jobs, stream=None) -> None:
     _check(lib().simplex_batch_launch(arr, len(jobs), _stream(stream)), "simplex_batch_launch")
 
 
-def serve_run_raw(jobs, arena_ptr, arena_bytes, mode, max_inflight=2, keep_outputs=False):
+def serve_run_raw(jobs, arena_ptr, arena_bytes, mode, max_inflight=4, keep_outputs=False):
     """jobs: list of (m, op, n, buf_in, arrival_s).  Returns (status, records)."""
     def p(x):
         return x if isinstance(x, int) else x.data_ptr()
@@ -247,7 +247,7 @@ def serve_run_raw(jobs, arena_ptr, arena_bytes, mode, max_inflight=2, keep_outpu
                 for i in range(len(jobs))]
 
 
-def serve_run(jobs, arena, mode, max_inflight=2, keep_outputs=False):
+def serve_run(jobs, arena, mode, max_inflight=4, keep_outputs=False):
     """Replay a job stream (see simplex_serve_run); `arena` is a uint8 device tensor."""
     rc, recs = serve_run_raw(jobs, arena.data_ptr(), arena.numel(), mode, max_inflight, keep_outputs)
     _check(rc, "simplex_serve_run")

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -407,20 +408,28 @@ constexpr TileCfg kBatchCa2 = {256, 256, 1};
 constexpr int kBatchCa3Ry = 64, kBatchCa3Rz = 16, kBatchCa3Rl = 2;
 constexpr TileCfg kBatchCa3 = {64, 128, (64 / kBatchCa3Ry) * (64 / kBatchCa3Rz)};
 constexpr int kBatchMaxJobs = 4096;   // jobs per launch (table capacity)
-constexpr int kBatchSlots = 16;       // table buffers per device
 
-// One table buffer: start[kBatchMaxJobs + 1] (padded to 256 bytes), then
-// the BatchJob array.  Pinned host staging plus its device copy; `ev`
-// marks the end of the launch that last read it.
-constexpr size_t kStartBytes = ((sizeof(uint32_t) * (kBatchMaxJobs + 1) + 255) / 256) * 256;
-constexpr size_t kSlotBytes = kStartBytes + sizeof(BatchJob) * kBatchMaxJobs;
+// Job tables live in a byte ring: pinned host staging plus a device copy of
+// the same size.  A launch takes the bytes it needs (the prefix array,
+// padded to 256 bytes, then the BatchJob array) right after the previous
+// one, wrapping to the start; each use is released when the event recorded
+// after its launch has completed.  Only when the ring is full does a launch
+// wait, on the host, for the oldest use.
+constexpr size_t kRingBytes = size_t(32) << 20;
+// Two zeroed 8 KiB buffers after the ring: input and output of the warm-up
+// steps of the serving loop (a 16^3 box each).
+constexpr size_t kWarmBytes = 16384;
 
 struct BatchRing {
+    struct Use {
+        size_t begin, end;
+        hipEvent_t ev;
+    };
     uint8_t *host = nullptr;
-    uint8_t *dev = nullptr;
-    hipEvent_t ev[kBatchSlots] = {};
-    bool used[kBatchSlots] = {};
-    int next = 0;
+    uint8_t *dev = nullptr;    // kRingBytes of tables, then kWarmBytes of zeros
+    size_t head = 0;
+    std::deque<Use> used;            // in allocation (ring) order
+    std::vector<hipEvent_t> spare;   // completed events for reuse
 };
 std::mutex g_batch_mu;
 std::map<int, BatchRing> g_rings;  // per device
@@ -431,18 +440,42 @@ int ring_for_device(BatchRing **out)
     if (hipGetDevice(&dev) != hipSuccess) return kEhip;
     BatchRing &R = g_rings[dev];
     if (!R.dev) {
-        if (hipHostMalloc((void **)&R.host, kSlotBytes * kBatchSlots, hipHostMallocDefault) != hipSuccess)
-            return kEhip;
-        if (hipMalloc((void **)&R.dev, kSlotBytes * kBatchSlots) != hipSuccess) {
+        if (hipHostMalloc((void **)&R.host, kRingBytes, hipHostMallocDefault) != hipSuccess) return kEhip;
+        if (hipMalloc((void **)&R.dev, kRingBytes + kWarmBytes) != hipSuccess) {
             (void)hipHostFree(R.host);
             R.host = nullptr;
             return kEhip;
         }
-        for (int i = 0; i < kBatchSlots; ++i) {
-            if (hipEventCreateWithFlags(&R.ev[i], hipEventDisableTiming) != hipSuccess) return kEhip;
-        }
+        if (hipMemset(R.dev + kRingBytes, 0, kWarmBytes) != hipSuccess) return kEhip;
     }
     *out = &R;
+    return kOk;
+}
+
+// Reserve `bytes` (a multiple of 256) of the ring at *off.
+int ring_reserve(BatchRing &R, size_t bytes, size_t *off)
+{
+    if (bytes > kRingBytes) return kErange;
+    const size_t a = (R.head + bytes > kRingBytes) ? 0 : R.head;
+    for (;;) {
+        // release finished uses, oldest first
+        while (!R.used.empty()) {
+            const hipError_t q = hipEventQuery(R.used.front().ev);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) return kEhip;
+            R.spare.push_back(R.used.front().ev);
+            R.used.pop_front();
+        }
+        bool overlap = false;
+        for (const BatchRing::Use &u : R.used) overlap = overlap || (u.begin < a + bytes && a < u.end);
+        if (!overlap) break;
+        // ring full here: wait for the oldest use (uses end in issue order of
+        // their events on the host; waiting on the oldest first is enough)
+        if (hipEventSynchronize(R.used.front().ev) != hipSuccess) return kEhip;
+        R.spare.push_back(R.used.front().ev);
+        R.used.pop_front();
+    }
+    *off = a;
     return kOk;
 }
 
@@ -453,18 +486,24 @@ struct BatchItem {
     uint32_t nwg;  // workgroups of the job
 };
 
-// One launch of a kernel class over items[0..cnt): fill a ring slot, copy
-// it to the device, launch.
+// One launch of a kernel class over items[0..cnt): fill ring bytes, copy
+// them to the device, launch, and mark the use with an event.
 int launch_batch_chunk(BatchRing &R, int kind, const BatchItem *items, int cnt, hipStream_t s)
 {
-    const int slot = R.next;
-    R.next = (R.next + 1) % kBatchSlots;
-    if (R.used[slot] && hipEventSynchronize(R.ev[slot]) != hipSuccess) return kEhip;
-    uint8_t *h = R.host + (size_t)slot * kSlotBytes;
-    uint8_t *d = R.dev + (size_t)slot * kSlotBytes;
-    uint32_t *start = reinterpret_cast<uint32_t *>(h);
-    BatchJob *jobs = reinterpret_cast<BatchJob *>(h + kStartBytes);
+    const size_t start_bytes = ((sizeof(uint32_t) * (size_t)(cnt + 1) + 255) / 256) * 256;
+    const size_t bytes = ((start_bytes + sizeof(BatchJob) * (size_t)cnt + 255) / 256) * 256;
     uint64_t acc = 0;
+    for (int i = 0; i < cnt; ++i) acc += items[i].nwg;
+    if (acc == 0) return kOk;
+    if (acc > kMaxWorkgroups) return kErange;
+    size_t off = 0;
+    int rc = ring_reserve(R, bytes, &off);
+    if (rc != kOk) return rc;
+    uint8_t *h = R.host + off;
+    uint8_t *d = R.dev + off;
+    uint32_t *start = reinterpret_cast<uint32_t *>(h);
+    BatchJob *jobs = reinterpret_cast<BatchJob *>(h + start_bytes);
+    acc = 0;
     for (int i = 0; i < cnt; ++i) {
         start[i] = (uint32_t)acc;
         jobs[i].P = items[i].P;
@@ -473,12 +512,9 @@ int launch_batch_chunk(BatchRing &R, int kind, const BatchItem *items, int cnt, 
         acc += items[i].nwg;
     }
     start[cnt] = (uint32_t)acc;
-    if (acc == 0) return kOk;
-    if (acc > kMaxWorkgroups) return kErange;
-    const size_t bytes = kStartBytes + sizeof(BatchJob) * (size_t)cnt;
     if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return kEhip;
     const uint32_t *dstart = reinterpret_cast<const uint32_t *>(d);
-    const BatchJob *djobs = reinterpret_cast<const BatchJob *>(d + kStartBytes);
+    const BatchJob *djobs = reinterpret_cast<const BatchJob *>(d + start_bytes);
     const uint32_t nwg = (uint32_t)acc, nj = (uint32_t)cnt;
     switch (kind) {
     case 0:
@@ -497,9 +533,49 @@ int launch_batch_chunk(BatchRing &R, int kind, const BatchItem *items, int cnt, 
         break;
     }
     if (hipGetLastError() != hipSuccess) return kEhip;
-    if (hipEventRecord(R.ev[slot], s) != hipSuccess) return kEhip;
-    R.used[slot] = true;
+    hipEvent_t ev = nullptr;
+    if (!R.spare.empty()) {
+        ev = R.spare.back();
+        R.spare.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        return kEhip;
+    }
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        R.spare.push_back(ev);
+        return kEhip;
+    }
+    R.used.push_back(BatchRing::Use{off, off + bytes, ev});
+    R.head = off + bytes;
     return kOk;
+}
+
+// Load the batched kernels' code and allocate the table ring before the
+// first batch (both take milliseconds on first use).
+int batch_prepare()
+{
+    hipFuncAttributes a;
+    const void *fns[] = {
+        reinterpret_cast<const void *>(&k_ca2_batch<256, 4, 16, 2, false>),
+        reinterpret_cast<const void *>(&k_ca2_batch<256, 4, 16, 2, true>),
+        reinterpret_cast<const void *>(&k_ca3_batch<64, kBatchCa3Ry, kBatchCa3Rz, kBatchCa3Rl, false>),
+        reinterpret_cast<const void *>(&k_ca3_batch<64, kBatchCa3Ry, kBatchCa3Rz, kBatchCa3Rl, true>),
+    };
+    for (const void *f : fns) {
+        if (hipFuncGetAttributes(&a, f) != hipSuccess) return kEhip;
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);   // and allocate the table ring now
+    BatchRing *R = nullptr;
+    return ring_for_device(&R);
+}
+
+// The warm-up buffers of this device (allocated with the ring).
+int warm_buffers(uint8_t **buf)
+{
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchRing *R = nullptr;
+    const int rc = ring_for_device(&R);
+    if (rc == kOk) *buf = R->dev + kRingBytes;
+    return rc;
 }
 
 int batch_launch(const simplex_job *jobs, int32_t njobs, void *stream)
@@ -864,7 +940,15 @@ int simplex_serve_run(const struct simplex_serve_job *jobs, int32_t njobs, void 
         records = local.data();
     }
     for (int32_t i = 0; i < njobs; ++i) records[i] = simplex_serve_record{-1.0, -1.0, -1.0, -1.0, 0, -1, kOk};
-    return serve_run(jobs, njobs, (uint8_t *)arena, arena_bytes, mode, max_inflight, keep_outputs, records);
+    if (mode == SMAP_SERVE_BATCHED) {
+        const int rc = batch_prepare();
+        if (rc != kOk) return rc;
+    }
+    uint8_t *warm = nullptr;
+    const int rc = warm_buffers(&warm);
+    if (rc != kOk) return rc;
+    return serve_run(jobs, njobs, (uint8_t *)arena, arena_bytes, mode, max_inflight, keep_outputs, records,
+                     warm);
 }
 
 int simplex_autotune(int m, int64_t n, int op, const void *buf_in, void *buf_out, int32_t reps,
