@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotune result file (read and appended)")
     ap.add_argument("--graph", type=int, default=0,
                     help="time H as replays of a captured graph of this many launches")
+    ap.add_argument("--gens", type=int, default=0,
+                    help="2-D automaton: time simplex_map_launch_steps advancing this many generations per call")
     ap.add_argument("--op", default=None, choices=["map", "accum", "hash", "hits"],
                     help="run this per-element op on the workload's m and n instead of its own")
     args = ap.parse_args()
@@ -283,6 +285,13 @@ def main():
                               cache_path=args.tune_cache, stream=stream)
         log(f"tuned: {tuned}")
     h_launch = lambda *a, **k: smap.map_launch(*a, beta=args.beta, **k)  # noqa: E731
+    gens = 1
+    if args.gens > 0:
+        if op != "ca2":
+            raise SystemExit("--gens applies to the 2-D automaton (workload c2)")
+        gens = args.gens
+        h_launch = lambda m_, n_, op_, s_, d_, stream=None: smap.map_launch_steps(  # noqa: E731
+            m_, n_, op_, gens, s_, d_, beta=args.beta, stream=stream)
     if args.graph > 0:
         # one replay = args.graph launches (automata: ping-pong, pointwise: repeated)
         K = args.graph if not u8 else args.graph + (args.graph % 2)
@@ -305,6 +314,10 @@ def main():
         log("timing BB" + (" as graph replays" if args.graph > 0 else ""))
         if args.graph > 0:
             bb_ms = graph_ms(True)
+        elif args.gens > 0:
+            bb_steps = lambda m_, n_, op_, s_, d_, stream=None: smap.bb_launch_steps(  # noqa: E731
+                m_, n_, op_, gens, s_, d_, stream=stream)
+            bb_ms = time_launches(step_fn(bb_steps), args.steps, args.warmup, stream)
         else:
             bb_ms = time_launches(step_fn(smap.bb_launch), args.steps, args.warmup, stream)
 
@@ -315,10 +328,10 @@ def main():
 
     info_h = smap.plan_info(m, n, op, beta=tuned["beta"] if tuned else args.beta)
     info_bb = smap.plan_info(m, n, op, use_bb=True)
-    alg_bytes = useful * BYTES_PER_ELEMENT[op]
+    alg_bytes = useful * BYTES_PER_ELEMENT[op]        # per pass over HBM
     achieved = alg_bytes / (h_ms * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload, op)
-    value = useful / (h_ms * 1e-3)
+    traffic = stored_traffic(args.workload, op) if args.gens == 0 else None
+    value = useful * gens / (h_ms * 1e-3)             # useful cell updates per second
 
     res = {
         "metric": "useful simplex elements/s (H map)",
@@ -335,10 +348,11 @@ def main():
         "data": "synthetic (seeded splitmix64)",
         "config": {"workload": f"{args.workload}: m={m} n={n} op={op}", "m": m, "n": n,
                    "op": op, "useful_elements": useful, "rho": info_h["rho"],
-                   "beta": info_h["beta"], "autotuned": tuned, "graph_launches": args.graph or None},
+                   "beta": info_h["beta"], "autotuned": tuned, "graph_launches": args.graph or None,
+                   "generations_per_call": gens},
         "hbm_gbs_algorithmic": achieved,
         "bb": None if bb_ms is None else {
-            "ms_per_step": bb_ms, "value": useful / (bb_ms * 1e-3),
+            "ms_per_step": bb_ms, "value": useful * gens / (bb_ms * 1e-3),
             "hbm_gbs_algorithmic": alg_bytes / (bb_ms * 1e-3) / 1e9},
         "h_vs_bb_speedup": None if bb_ms is None else bb_ms / h_ms,
         "tiles": {"useful": info_h["useful_tiles"], "h_launched": info_h["launched_tiles"],
@@ -351,7 +365,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
-            "kernel": f"{op} H launch",
+            "kernel": f"{op} H launch" + (f" ({gens} generations per call, rho 128, halo 16)" if args.gens else ""),
             "kernel_sha": kernel_sha(op),
             "bytes_per_launch": alg_bytes,
             "copy_gbs": None if copy is None else copy["gbs"],

@@ -224,6 +224,29 @@ int simplex_graph_destroy(void *graph);
 /* Static, human-readable text for a status code. */
 const char *simplex_strerror(int status);
 
+/* ---- several generations per launch -------------------------------------
+ *
+ * `steps` generations of the automaton (Section 5.1 runs a fixed number of
+ * steps) with temporal blocking: each pass loads a tile plus a halo of 16
+ * cells into LDS and advances it up to 16 generations there, so HBM is
+ * read and written once per pass instead of once per generation.
+ * Supported: m = 2 with SMAP_OP_CA2 (others: SMAP_EUNSUPPORTED).
+ *
+ * buf_out receives the state after `steps` generations of buf_in (layout
+ * and rules as for simplex_map_launch; the buffers must not overlap).
+ * With steps <= 16 one pass runs and buf_in is left unchanged; with more,
+ * passes alternate between the two buffers (an odd number of passes, the
+ * last one writing buf_out) and buf_in's simplex cells are overwritten
+ * with intermediate states.  Cells outside the simplex are never written.
+ * steps < 1 gives SMAP_EINVAL; other errors as for simplex_map_launch.
+ */
+int simplex_map_launch_steps(int m, int64_t n, int r, int beta, int op, int32_t steps, void *buf_in,
+                             void *buf_out, void *stream);
+
+/* The same passes with the bounding-box map (the baseline). */
+int simplex_bb_launch_steps(int m, int64_t n, int op, int32_t steps, void *buf_in, void *buf_out,
+                            void *stream);
+
 /* ---- batched launch ---------------------------------------------------
  *
  * One job of a batched launch: one automaton step over Delta_n^m with the

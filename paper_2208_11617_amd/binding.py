@@ -23,7 +23,8 @@ EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_plan_info", "simplex_plan_tiles", "simplex_set_tile",
            "simplex_strerror", "simplex_batch_launch", "simplex_serve_run",
            "simplex_autotune", "simplex_autotune_reset", "simplex_graph_create",
-           "simplex_graph_launch", "simplex_graph_destroy")
+           "simplex_graph_launch", "simplex_graph_destroy", "simplex_map_launch_steps",
+           "simplex_bb_launch_steps")
 
 SERVE_SEQUENTIAL, SERVE_BATCHED = 0, 1
 
@@ -128,6 +129,10 @@ def lib():
     L.simplex_graph_launch.restype = ci
     L.simplex_graph_destroy.argtypes = [vp]
     L.simplex_graph_destroy.restype = ci
+    L.simplex_map_launch_steps.argtypes = [ci, i64, ci, ci, ci, ctypes.c_int32, vp, vp, vp]
+    L.simplex_map_launch_steps.restype = ci
+    L.simplex_bb_launch_steps.argtypes = [ci, i64, ci, ctypes.c_int32, vp, vp, vp]
+    L.simplex_bb_launch_steps.restype = ci
     L.simplex_strerror.argtypes = [ci]
     L.simplex_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -298,3 +303,21 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def map_launch_steps(m, n, op, steps, buf_in, buf_out, r=0, beta=0, stream=None) -> None:
+    """`steps` generations with the H map (several per pass; see the header)."""
+    _check(lib().simplex_map_launch_steps(m, n, r, beta, _op(op), steps, _ptr(buf_in), _ptr(buf_out),
+                                          _stream(stream)), "simplex_map_launch_steps")
+
+
+def bb_launch_steps(m, n, op, steps, buf_in, buf_out, stream=None) -> None:
+    _check(lib().simplex_bb_launch_steps(m, n, _op(op), steps, _ptr(buf_in), _ptr(buf_out),
+                                         _stream(stream)), "simplex_bb_launch_steps")
+
+
+def launch_steps_raw(m, n, op, steps, in_ptr, out_ptr, use_bb=False) -> int:
+    L = lib()
+    if use_bb:
+        return L.simplex_bb_launch_steps(m, n, _op(op), steps, in_ptr, out_ptr, None)
+    return L.simplex_map_launch_steps(m, n, 0, 0, _op(op), steps, in_ptr, out_ptr, None)

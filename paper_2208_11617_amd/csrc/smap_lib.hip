@@ -18,6 +18,7 @@
 #include "../../include/simplexmap.h"
 #include "smap_batch.hpp"
 #include "smap_ca2.hpp"
+#include "smap_ca2k.hpp"
 #include "smap_ca3.hpp"
 #include "smap_plan.hpp"
 #include "smap_point.hpp"
@@ -793,6 +794,65 @@ int graph_create(int m, int64_t n, int r, int beta, int op, bool bb, const void 
     return kOk;
 }
 
+// ---- several generations per pass (CA2) ------------------------------------
+
+constexpr int kStepsRho = 128, kStepsKh = 16;   // tile side and halo (= generations per pass)
+constexpr TileCfg kStepsTile = {kStepsRho, 256, 1};
+
+int steps_launch(int m, int64_t n, int r, int beta, int op, int32_t steps, void *a, void *b,
+                 void *stream, bool bb)
+{
+    if (m != 2 || op != OP_CA2) return (check_op(m, n, op) != kOk) ? kEinval : kEunsupported;
+    if (steps < 1) return kEinval;
+    int rc = check_op(m, n, op);
+    if (rc != kOk) return rc;
+    int bt = 0;
+    if (!bb) {
+        rc = resolve_rb(m, r, beta, &bt);
+        if (rc != kOk) return rc;
+    }
+    rc = check_buffers(m, n, op, a, b);
+    if (rc != kOk) return rc;
+    Plan P;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        rc = plan_for(m, n, bt, bb, 1, kStepsTile, &P, nullptr);
+    }
+    if (rc != kOk) return rc;
+    if (P.total == 0) return kOk;
+    const uint32_t kb = (uint32_t)P.kbox;
+    const dim3 grid = bb ? dim3(kb, kb, 1) : dim3(P.total, 1, 1);
+    P.grid[0] = grid.x;
+    P.grid[1] = grid.y;
+    P.grid[2] = grid.z;
+    P.nwg = grid.x * grid.y * grid.z;
+    P.grid_div[0] = make_divu(grid.x);
+    P.grid_div[1] = make_divu(grid.y);
+    P.remap = bb ? 0u : 1u;
+    // passes of at most kStepsKh generations, alternating a -> b -> a ...;
+    // an odd number of passes, so that the last one writes b
+    int passes = (steps + kStepsKh - 1) / kStepsKh;
+    if (passes % 2 == 0) ++passes;
+    hipStream_t s = (hipStream_t)stream;
+    int left = steps;
+    for (int i = 0; i < passes; ++i) {
+        const int g = (left + (passes - i) - 1) / (passes - i);   // spread evenly, 1..kStepsKh
+        const uint8_t *src = (const uint8_t *)((i & 1) ? b : a);
+        uint8_t *dst = (uint8_t *)((i & 1) ? a : b);
+        const bool safe = n < 15;
+        if (bb) {
+            if (safe) hipLaunchKernelGGL((k_ca2k<kStepsRho, kStepsKh, true, true>), grid, dim3(256), 0, s, P, src, dst, g);
+            else hipLaunchKernelGGL((k_ca2k<kStepsRho, kStepsKh, true, false>), grid, dim3(256), 0, s, P, src, dst, g);
+        } else {
+            if (safe) hipLaunchKernelGGL((k_ca2k<kStepsRho, kStepsKh, false, true>), grid, dim3(256), 0, s, P, src, dst, g);
+            else hipLaunchKernelGGL((k_ca2k<kStepsRho, kStepsKh, false, false>), grid, dim3(256), 0, s, P, src, dst, g);
+        }
+        if (hipGetLastError() != hipSuccess) return kEhip;
+        left -= g;
+    }
+    return kOk;
+}
+
 }  // namespace
 
 extern "C" {
@@ -986,6 +1046,18 @@ int simplex_graph_destroy(void *graph)
     if (h->graph && hipGraphDestroy(h->graph) != hipSuccess) rc = kEhip;
     delete h;
     return rc;
+}
+
+int simplex_map_launch_steps(int m, int64_t n, int r, int beta, int op, int32_t steps, void *buf_in,
+                             void *buf_out, void *stream)
+{
+    return steps_launch(m, n, r, beta, op, steps, buf_in, buf_out, stream, false);
+}
+
+int simplex_bb_launch_steps(int m, int64_t n, int op, int32_t steps, void *buf_in, void *buf_out,
+                            void *stream)
+{
+    return steps_launch(m, n, 0, 0, op, steps, buf_in, buf_out, stream, true);
 }
 
 const char *simplex_strerror(int status)

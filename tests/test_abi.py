@@ -179,3 +179,15 @@ def test_autotune_and_graph_argument_errors():
     assert L.simplex_graph_create(3, 100, 0, 0, 4, 1, 4096, 1 << 20, 2, ctypes.byref(h)) == E   # CA2 with m = 3
     assert L.simplex_graph_launch(None, None) == E
     assert L.simplex_graph_destroy(None) == smap.OK
+
+
+def test_launch_steps_argument_errors():
+    E, U = smap.EINVAL, smap.EUNSUPPORTED
+    a, b = 4096, 1 << 24
+    assert smap.launch_steps_raw(2, 100, "ca2", 0, a, b) == E          # steps < 1
+    assert smap.launch_steps_raw(2, 100, "ca2", -3, a, b, use_bb=True) == E
+    assert smap.launch_steps_raw(3, 40, "ca3", 4, a, b) == U           # only the 2-D automaton
+    assert smap.launch_steps_raw(2, 100, "accum", 4, a, b) == U
+    assert smap.launch_steps_raw(2, 100, "ca3", 4, a, b) == E          # CA3 needs m = 3
+    assert smap.launch_steps_raw(2, 100, "ca2", 4, a, a + 100) == E     # overlapping buffers
+    assert smap.launch_steps_raw(2, 100, "ca2", 4, 0, b) == E           # NULL input

@@ -1,0 +1,87 @@
+"""Several automaton generations per pass (temporal blocking) against the
+oracle applied generation by generation; bit-exact, H and BB, with the
+sentinel outside the simplex intact and the input untouched when one pass
+suffices."""
+import numpy as np
+import pytest
+
+import simplex_inputs as si
+from oracle import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def smap():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_11617_amd import binding
+    binding.lib()
+    return binding
+
+
+def oracle_steps(n, inp, steps):
+    cur = inp.copy()
+    for _ in range(steps):
+        nxt = si.sentinel_box(2, n, np.uint8)
+        oracle.apply(2, n, "ca2", cur, nxt)
+        cur = nxt
+    return cur
+
+
+SIZES = [0, 1, 5, 14, 15, 16, 63, 100, 127, 128, 129, 159, 160, 161, 255, 300, 700]
+STEPS = [1, 2, 7, 16, 17, 33, 40]
+
+
+@pytest.mark.parametrize("kind", ["h", "bb"])
+def test_steps_match_oracle(smap, kind):
+    launch = smap.map_launch_steps if kind == "h" else smap.bb_launch_steps
+    for n in SIZES:
+        inp = si.box(2, n, "bern", 8000 + n, p=0.35)
+        inside = si.inside_mask(2, n)
+        for steps in STEPS:
+            if n > 300 and steps > 17:
+                continue
+            say(f"{kind} n={n} steps={steps}")
+            want = oracle_steps(n, inp, steps)
+            d_in = torch.from_numpy(inp.copy()).cuda()
+            d_out = torch.from_numpy(si.sentinel_box(2, n, np.uint8)).cuda()
+            launch(2, n, "ca2", steps, d_in, d_out)
+            torch.cuda.synchronize()
+            got = d_out.cpu().numpy()
+            assert np.array_equal(got, want), (kind, n, steps)
+            after_in = d_in.cpu().numpy()
+            assert np.array_equal(after_in[~inside], inp[~inside])      # outside never written
+            if steps <= 16:
+                assert np.array_equal(after_in, inp)                   # one pass: input untouched
+
+
+def test_steps_workload_size_matches_single_steps(smap):
+    """n = 16384: 16 generations in one pass equal 16 single-step launches."""
+    w = si.WORKLOADS["c2"]
+    n = w["n"]
+    a = si.box_torch(2, n, "bern", w["seed"], p=w["p"], device="cuda")
+    b = si.sentinel_box_torch(2, n, True, device="cuda")
+    orig = a.clone()
+    ref_a, ref_b = a.clone(), b.clone()
+    say("single steps x16")
+    for i in range(16):
+        src, dst = (ref_a, ref_b) if i % 2 == 0 else (ref_b, ref_a)
+        smap.map_launch(2, n, "ca2", src, dst)
+    out = si.sentinel_box_torch(2, n, True, device="cuda")
+    say("one pass of 16")
+    smap.map_launch_steps(2, n, "ca2", 16, a, out)
+    torch.cuda.synchronize()
+    r = torch.arange(n + 1, device="cuda")
+    inside = (r.view(-1, 1) + r.view(1, -1)) <= n          # x_1 + x_2 <= n (symmetric)
+    # 16 single steps end in ref_a; outside the simplex ref_a keeps the input's
+    # poison and `out` its sentinel, neither written
+    assert torch.equal(out[inside], ref_a[inside])
+    assert bool((out[~inside] == si.SENTINEL_U8).all())
+    assert torch.equal(a, orig)             # one pass leaves the input untouched
