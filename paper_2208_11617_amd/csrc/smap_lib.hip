@@ -55,7 +55,7 @@ constexpr PointShape kPointShapes[] = {
 
 // CA3 shapes: (rho, threads) -> rows RY (y), planes RZ (z), rows per lane RL.
 #ifndef SMAP_CA3_RZ
-#define SMAP_CA3_RZ 16
+#define SMAP_CA3_RZ 8
 #endif
 struct Ca3Shape {
     int rho, wg, ry, rz, rl, sub;
