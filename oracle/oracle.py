@@ -35,7 +35,7 @@ def build() -> str:
     """Compile the oracle with gcc into ``oracle/liboracle.so`` (always rebuilds)."""
     tmp = LIB + ".tmp"
     subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
-                    SRC, "-o", tmp], check=True)
+                    SRC, "-o", tmp, "-lm"], check=True)
     os.replace(tmp, LIB)
     return LIB
 
@@ -70,6 +70,8 @@ def _load():
     lib.oracle_fnv1a_words.restype = ctypes.c_uint32
     lib.oracle_fmix32.argtypes = [ctypes.c_uint32]
     lib.oracle_fmix32.restype = ctypes.c_uint32
+    lib.oracle_edm.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, i64p]
+    lib.oracle_edm.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -159,3 +161,18 @@ def fnv1a_words(x) -> int:
 
 def fmix32(h: int) -> int:
     return int(_load().oracle_fmix32(h & 0xFFFFFFFF))
+
+
+def edm(n: int, pts) -> np.ndarray:
+    """Euclidean distance matrix on Delta_n^2 (see oracle_edm): a float64
+    (n+1, n+1) box, NaN outside the simplex.  pts: float32 (n+1, 3)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float32)
+    assert pts.shape == (n + 1, 3)
+    out = np.full((n + 1, n + 1), np.nan, dtype=np.float64)
+    visited = ctypes.c_int64(0)
+    rc = _load().oracle_edm(n, pts.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p),
+                            ctypes.byref(visited))
+    if rc != 0:
+        raise ValueError(f"oracle_edm failed: {rc}")
+    assert visited.value == (n + 1) * (n + 2) // 2
+    return out

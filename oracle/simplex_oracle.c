@@ -20,7 +20,7 @@
  *   Cells outside Delta_n^m are never read as data and never written.
  *
  *   Operations (the test kernels of Section 5.1, Table tab:tests, plus a
- *   hit counter and a coordinate hash):
+ *   hit counter and a coordinate hash; the EDM test is oracle_edm below):
  *     MAP    -- visit every element, write nothing.
  *     ACCUM  -- out[i] = in[i] + 1  (uint32, wrapping mod 2^32).
  *     HITS   -- out[i] = out[i] + 1 (uint32): counts how often each element
@@ -44,11 +44,26 @@
  * Enumeration follows Eq. 1 directly: nested loops, x_m outermost and x_1
  * innermost, each upper bound being n minus the coordinates already fixed.
  */
-#include <stdint.h>
+#include <math.h>
 #include <stddef.h>
+#include <stdint.h>
 
 enum { OR_MAP = 0, OR_ACCUM = 1, OR_HITS = 2, OR_HASH = 3, OR_CA2 = 4, OR_CA3 = 5 };
 enum { OR_OK = 0, OR_EINVAL = -1 };
+
+/* ---- EDM (Section 5.1, Table tab:tests, test 3) ------------------------------
+ *
+ * The Euclidean distance matrix on the 2-simplex: the element at location
+ * (i, j) holds the distance d(p_i, p_j) between two points of a set
+ * p_0 .. p_n.  The paper does not fix the point dimension or the
+ * placement of (i, j) in Delta_n^2; read here as: points in R^3, and the
+ * element x = (x_1, x_2) holds the pair (i, j) = (x_1, n - x_2), so that
+ * x_1 + x_2 <= n is exactly i <= j (the upper triangle with its diagonal,
+ * the diagonal being x_1 + x_2 = n).  The oracle evaluates the definition
+ * sqrt(sum_k (p_i[k] - p_j[k])^2) in double precision from the float
+ * coordinates; out is a double (n+1)^2 box, written on Delta_n^2 only.
+ */
+int oracle_edm(int64_t n, const float *pts, double *out, int64_t *visited);
 
 /* ---- hash32 ------------------------------------------------------------ */
 
@@ -304,4 +319,25 @@ int64_t oracle_count(int m, int64_t n)
     int64_t cnt = 0;
     if (oracle_apply(m, n, OR_MAP, NULL, NULL, &cnt) != OR_OK) return -1;
     return cnt;
+}
+
+
+int oracle_edm(int64_t n, const float *pts, double *out, int64_t *visited)
+{
+    if (n < 0 || pts == NULL || out == NULL) return OR_EINVAL;
+    int64_t cnt = 0;
+    for (int64_t x2 = 0; x2 <= n; ++x2) {
+        for (int64_t x1 = 0; x1 <= n - x2; ++x1) {
+            const int64_t i = x1, j = n - x2;
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double d = (double)pts[3 * i + k] - (double)pts[3 * j + k];
+                s += d * d;
+            }
+            out[x1 + x2 * (n + 1)] = sqrt(s);
+            ++cnt;
+        }
+    }
+    if (visited) *visited = cnt;
+    return OR_OK;
 }

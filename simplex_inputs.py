@@ -243,3 +243,11 @@ def sentinel_box_torch(m: int, n: int, u8: bool, device="cuda"):
     if u8:
         return torch.full(shape, SENTINEL_U8, dtype=torch.uint8, device=device)
     return torch.full(shape, SENTINEL_U32 - (1 << 32), dtype=torch.int32, device=device)
+
+
+def points(n: int, seed: int, dim: int = 3) -> np.ndarray:
+    """n+1 points in [0, 1)^dim, float32: coordinate c of point k is the top
+    24 bits of splitmix64 output k*dim + c, divided by 2^24 (exact in
+    float32)."""
+    z = splitmix64(seed, 0, (n + 1) * dim)
+    return ((z >> np.uint64(40)).astype(np.float64) / 16777216.0).astype(np.float32).reshape(n + 1, dim)

@@ -345,3 +345,70 @@ def test_bernoulli_thresholds():
     assert si.bern_threshold(0.3) == 1288490188
     assert si.bern_threshold(0.2) == 858993459
     assert si.bern_threshold(0.25) == 1073741824
+
+
+# ---- EDM (Section 5.1, test 3): pins against closed forms and invariants ----
+
+def _edm_pair(out, n, i, j):
+    """The oracle's value for the pair (i, j), i <= j: element (x_1, x_2) = (i, n - j)."""
+    return out[n - j, i]          # numpy axes (x_2, x_1)
+
+
+def test_edm_collinear_points_give_index_gaps():
+    n = 40
+    pts = np.zeros((n + 1, 3), dtype=np.float32)
+    pts[:, 0] = np.arange(n + 1)
+    out = oracle.edm(n, pts)
+    for i in range(n + 1):
+        for j in range(i, n + 1):
+            assert _edm_pair(out, n, i, j) == j - i
+
+
+@pytest.mark.parametrize("step,norm", [((3, 4, 0), 5), ((2, 3, 6), 7), ((1, 4, 8), 9)])
+def test_edm_pythagorean_directions(step, norm):
+    n = 25
+    pts = (np.arange(n + 1)[:, None] * np.array(step)[None, :]).astype(np.float32)
+    out = oracle.edm(n, pts)
+    for i in range(0, n + 1, 3):
+        for j in range(i, n + 1, 2):
+            assert _edm_pair(out, n, i, j) == norm * (j - i)
+
+
+def test_edm_layout_diagonal_outside_and_symmetry_of_definition():
+    n = 30
+    pts = si.points(n, 77)
+    out = oracle.edm(n, pts)
+    x1 = np.arange(n + 1)[None, :]
+    x2 = np.arange(n + 1)[:, None]
+    inside = x1 + x2 <= n
+    assert np.isnan(out[~inside]).all() and not np.isnan(out[inside]).any()
+    assert (out[x1 + x2 == n] == 0.0).all()                   # i == j
+    # d(p_i, p_j) for i < j equals the same definition with the roles swapped
+    for i, j in [(0, n), (3, 17), (11, 12), (29, 30)]:
+        d = np.sqrt(((pts[j].astype(np.float64) - pts[i]) ** 2).sum())
+        assert abs(_edm_pair(out, n, i, j) - d) <= 1e-15
+
+
+def test_edm_triangle_inequality_and_exact_scaling():
+    n = 36
+    pts = si.points(n, 91)
+    out = oracle.edm(n, pts)
+    D = np.zeros((n + 1, n + 1))
+    for i in range(n + 1):
+        for j in range(i, n + 1):
+            D[i, j] = D[j, i] = _edm_pair(out, n, i, j)
+    viol = D[:, None, :] > D[:, :, None] + D[None, :, :] + 1e-12   # d(i,k) > d(i,j) + d(j,k)
+    assert not viol.any()
+    out2 = oracle.edm(n, (pts * 2).astype(np.float32))        # exact in float32
+    inside = ~np.isnan(out)
+    assert np.array_equal(out2[inside], 2 * out[inside])
+    shifted = (pts + np.float32(0.5)).astype(np.float32)      # exact: values are k / 2^24 < 1
+    out3 = oracle.edm(n, shifted)
+    assert np.allclose(out3[inside], out[inside], rtol=0, atol=1e-15)
+
+
+def test_points_generator_is_exact_and_seeded():
+    a, b = si.points(10, 5), si.points(10, 5)
+    assert a.dtype == np.float32 and a.shape == (11, 3) and np.array_equal(a, b)
+    assert ((a * 16777216.0) == np.round(a * 16777216.0)).all() and (a >= 0).all() and (a < 1).all()
+    assert not np.array_equal(a, si.points(10, 6))
