@@ -402,9 +402,10 @@ def test_edm_triangle_inequality_and_exact_scaling():
     out2 = oracle.edm(n, (pts * 2).astype(np.float32))        # exact in float32
     inside = ~np.isnan(out)
     assert np.array_equal(out2[inside], 2 * out[inside])
-    shifted = (pts + np.float32(0.5)).astype(np.float32)      # exact: values are k / 2^24 < 1
-    out3 = oracle.edm(n, shifted)
-    assert np.allclose(out3[inside], out[inside], rtol=0, atol=1e-15)
+    coarse = (np.floor(pts * 4096.0) / 4096.0).astype(np.float32)   # 12-bit fractions
+    shifted = (coarse + np.float32(0.5)).astype(np.float32)          # exact in float32
+    assert np.array_equal(shifted - np.float32(0.5), coarse)
+    assert np.array_equal(oracle.edm(n, shifted)[inside], oracle.edm(n, coarse)[inside])
 
 
 def test_points_generator_is_exact_and_seeded():
