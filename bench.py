@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
 
 # algorithmic HBM bytes per useful element (read + write)
-BYTES_PER_ELEMENT = {"accum": 8, "ca2": 2, "ca3": 2, "hash": 4, "hits": 8, "map": 0}
+BYTES_PER_ELEMENT = {"accum": 8, "ca2": 2, "ca3": 2, "hash": 4, "hits": 8, "map": 0, "edm": 4}
 
 # kernel sources whose change invalidates stored counter readings, per op
 KERNEL_SOURCES = {
@@ -228,7 +228,7 @@ def main():
                     help="time H as replays of a captured graph of this many launches")
     ap.add_argument("--gens", type=int, default=0,
                     help="2-D automaton: time simplex_map_launch_steps advancing this many generations per call")
-    ap.add_argument("--op", default=None, choices=["map", "accum", "hash", "hits"],
+    ap.add_argument("--op", default=None, choices=["map", "accum", "hash", "hits", "edm"],
                     help="run this per-element op on the workload's m and n instead of its own")
     args = ap.parse_args()
 
@@ -250,6 +250,8 @@ def main():
     if args.op is not None and args.op != w["op"]:
         # the same domain with another per-element op (MAP shows the map alone)
         w.update(op=args.op, dist="u31" if args.op == "accum" else None, p=None)
+    if w["op"] == "edm":
+        w["dist"] = None          # the input is a point set, generated below
     m, n, op = w["m"], w["n"], w["op"]
     u8 = op.startswith("ca")
     dev = torch.device("cuda:0")
@@ -259,7 +261,11 @@ def main():
 
     log(f"generating {args.workload}: m={m} n={n} op={op}")
     bufs = []
-    if w["dist"] is not None:
+    if op == "edm":
+        if m != 2:
+            raise SystemExit("--op edm needs a 2-D workload (c1 or c2)")
+        bufs.append(torch.from_numpy(si.points(n, w["seed"])).to(dev))   # n+1 points in R^3
+    elif w["dist"] is not None:
         bufs.append(si.box_torch(m, n, w["dist"], w["seed"], p=w["p"], device=dev))
     out_a = si.sentinel_box_torch(m, n, u8, device=dev)
     torch.cuda.synchronize()
@@ -269,7 +275,7 @@ def main():
             if u8:   # ping-pong: in -> a, a -> in, ...
                 src, dst = (bufs[0], out_a) if i % 2 == 0 else (out_a, bufs[0])
                 launch(m, n, op, src, dst, stream=stream)
-            elif op == "accum":
+            elif op in ("accum", "edm"):
                 launch(m, n, op, bufs[0], out_a, stream=stream)
             elif op == "map":
                 launch(m, n, op, None, None, stream=stream)
@@ -376,7 +382,7 @@ def main():
     }
     if op == "map":
         res["roofline"] = None   # the map alone moves no bytes: see tiles and timings
-    if not args.no_cpu:
+    if not args.no_cpu and op != "edm":
         log("cpu_baseline: oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)

@@ -37,6 +37,13 @@
  *                 m = 2 only.                                   in, out: uint8
  *   SMAP_OP_CA3   one step of rule B6/S567 over the 26-neighbourhood,
  *                 m = 3 only.                                   in, out: uint8
+ *   SMAP_OP_EDM   Euclidean distance matrix (Section 5.1, test 3), m = 2
+ *                 only: out[x] = float32 distance between points i = x_1
+ *                 and j = n - x_2 (x_1 + x_2 <= n is i <= j, the diagonal
+ *                 i = j being x_1 + x_2 = n), computed in float32 as
+ *                 sqrtf(dx^2 + dy^2 + dz^2).  in: n+1 points in R^3 as
+ *                 float32 (x, y, z) triples, 16-byte aligned; out: float32
+ *                 (n+1)^2 box.
  *   For CA ops the cells in the simplex must hold 0 or 1 (1 = alive);
  *   neighbours outside the simplex count as dead; in and out must not
  *   overlap (ping-pong between two buffers across steps).
@@ -71,6 +78,7 @@ extern "C" {
 #define SMAP_OP_HASH  3
 #define SMAP_OP_CA2   4
 #define SMAP_OP_CA3   5
+#define SMAP_OP_EDM   6
 
 /* Description of one launch plan (filled by simplex_plan_info). */
 struct simplex_plan_info {

@@ -14,9 +14,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsimplexmap.so")
 
 OK, EINVAL, EUNSUPPORTED, ERANGE, EHIP = 0, -1, -2, -3, -4
-OP_MAP, OP_ACCUM, OP_HITS, OP_HASH, OP_CA2, OP_CA3 = range(6)
+OP_MAP, OP_ACCUM, OP_HITS, OP_HASH, OP_CA2, OP_CA3, OP_EDM = range(7)
 OPS = {"map": OP_MAP, "accum": OP_ACCUM, "hits": OP_HITS, "hash": OP_HASH,
-       "ca2": OP_CA2, "ca3": OP_CA3}
+       "ca2": OP_CA2, "ca3": OP_CA3, "edm": OP_EDM}
 
 # names declared in include/simplexmap.h
 EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",

@@ -223,8 +223,8 @@ int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C
 int check_op(int m, int64_t n, int op)
 {
     if (m < 2 || m > 4 || n < 0) return kEinval;
-    if (op < OP_MAP || op > OP_CA3) return kEinval;
-    if (op == OP_CA2 && m != 2) return kEinval;
+    if (op < OP_MAP || op > OP_EDM) return kEinval;
+    if ((op == OP_CA2 || op == OP_EDM) && m != 2) return kEinval;
     if (op == OP_CA3 && m != 3) return kEinval;
     return kOk;
 }
@@ -235,6 +235,7 @@ int check_buffers(int m, int64_t n, int op, const void *in, const void *out)
     if (!box_elems(m, n, &elems)) return kErange;
     if (op == OP_ACCUM && (!in || !out)) return kEinval;
     if ((op == OP_HITS || op == OP_HASH) && !out) return kEinval;
+    if (op == OP_EDM && (!in || !out || ((uintptr_t)in & 15u) != 0)) return kEinval;  // 16-byte aligned points
     if (op == OP_CA2 || op == OP_CA3) {
         if (!in || !out) return kEinval;
         const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
@@ -282,6 +283,15 @@ int dispatch_point(int op, int m, int rho, const Plan &P, dim3 grid, const void 
     case OP_ACCUM: return dispatch_point_shape<OP_ACCUM, BB>(m, rho, P, grid, in, out, s);
     case OP_HITS: return dispatch_point_shape<OP_HITS, BB>(m, rho, P, grid, in, out, s);
     case OP_HASH: return dispatch_point_shape<OP_HASH, BB>(m, rho, P, grid, in, out, s);
+    case OP_EDM:
+        if (m != 2) return kEinval;
+        switch (rho) {
+        case 32: launch_point<2, 32, 256, 1, OP_EDM, BB>(P, grid, in, out, s); return kOk;
+        case 16: launch_point<2, 16, 64, 1, OP_EDM, BB>(P, grid, in, out, s); return kOk;
+        case 64: launch_point<2, 64, 256, 1, OP_EDM, BB>(P, grid, in, out, s); return kOk;
+        case 128: launch_point<2, 128, 256, 2, OP_EDM, BB>(P, grid, in, out, s); return kOk;
+        }
+        return kEunsupported;
     }
     return kEinval;
 }

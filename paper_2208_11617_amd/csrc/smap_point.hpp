@@ -1,6 +1,10 @@
-// smap_point.hpp -- per-element kernels MAP, ACCUM, HITS and HASH (uint32).
+// smap_point.hpp -- per-element kernels MAP, ACCUM, HITS, HASH (uint32) and
+// EDM (float32).
 //
-// The test kernels of Section 5.1, Table tab:tests, plus HITS and HASH.
+// The test kernels of Section 5.1, Table tab:tests, plus HITS and HASH.  EDM
+// (2-D only) stores at element (x_1, x_2) the distance between points
+// i = x_1 and j = n - x_2 of a set of n+1 points in R^3 (x_1 + x_2 <= n is
+// i <= j), in float32: three differences, a sum of squares, sqrtf.
 // The tile comes from the H decode (one 1-D grid over the fused native +
 // shell pieces) or from the BB grid coordinates; BB tiles fully outside the
 // simplex exit before touching memory.
@@ -16,7 +20,7 @@
 
 namespace smap {
 
-enum Op { OP_MAP = 0, OP_ACCUM = 1, OP_HITS = 2, OP_HASH = 3, OP_CA2 = 4, OP_CA3 = 5 };
+enum Op { OP_MAP = 0, OP_ACCUM = 1, OP_HITS = 2, OP_HASH = 3, OP_CA2 = 4, OP_CA3 = 5, OP_EDM = 6 };
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 constexpr int ipowc(int b, int e) { return e == 0 ? 1 : b * ipowc(b, e - 1); }
@@ -119,6 +123,35 @@ __global__ __launch_bounds__(NT) void k_point(const Plan P, const uint32_t *in, 
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) r[j] += 1u;
+            } else if (OP == OP_EDM) {
+                if constexpr (M == 2) {
+                    // element (x_1, x_2) holds d(p_i, p_j), i = x_1, j = n - x_2
+                    const float *pts = reinterpret_cast<const float *>(in);
+                    const int32_t jj = n - xr[1];
+                    const float qx = pts[3 * jj], qy = pts[3 * jj + 1], qz = pts[3 * jj + 2];
+                    auto dist = [&](float a, float b, float c) {
+                        const float dx = a - qx, dy = b - qy, dz = c - qz;
+                        return __float_as_uint(sqrtf(dx * dx + dy * dy + dz * dz));
+                    };
+                    const int32_t i0 = x0[0] + lx;
+                    if (v >= 4) {  // points i0 .. i0+3: 12 floats, 16-byte aligned (i0 % 4 == 0)
+                        const float4 *q4 = reinterpret_cast<const float4 *>(pts + 3 * i0);
+                        const float4 a = q4[0], b = q4[1], c = q4[2];
+                        r[0] = dist(a.x, a.y, a.z);
+                        r[1] = dist(a.w, b.x, b.y);
+                        r[2] = dist(b.z, b.w, c.x);
+                        r[3] = dist(c.y, c.z, c.w);
+                    } else {       // only the points inside: no read past point n
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float *p = pts + 3 * (i0 + (j < v ? j : 0));
+                            r[j] = dist(p[0], p[1], p[2]);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) r[j] = 0u;
+                }
             } else {  // OP_HASH
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {

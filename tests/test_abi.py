@@ -64,7 +64,11 @@ def test_argument_errors(launch):
     assert call(1, 10, smap.OP_ACCUM, FAKE, FAKE) == smap.EINVAL     # m = 1: no map needed
     assert call(5, 10, smap.OP_ACCUM, FAKE, FAKE) == smap.EINVAL
     assert call(2, -1, smap.OP_ACCUM, FAKE, FAKE) == smap.EINVAL
-    assert call(2, 10, 6, FAKE, FAKE) == smap.EINVAL                  # unknown op
+    assert call(2, 10, 7, FAKE, FAKE) == smap.EINVAL                  # unknown op
+    assert call(3, 10, smap.OP_EDM, FAKE, FAKE) == smap.EINVAL         # EDM needs m = 2
+    assert call(2, 10, smap.OP_EDM, None, FAKE) == smap.EINVAL         # no points
+    assert call(2, 10, smap.OP_EDM, FAKE, None) == smap.EINVAL
+    assert call(2, 10, smap.OP_EDM, FAKE + 4, FAKE) == smap.EINVAL     # points not 16-byte aligned
     assert call(2, 10, -1, FAKE, FAKE) == smap.EINVAL
     assert call(3, 10, smap.OP_CA2, FAKE, FAKE + 4096) == smap.EINVAL  # CA2 needs m = 2
     assert call(2, 10, smap.OP_CA3, FAKE, FAKE + 4096) == smap.EINVAL  # CA3 needs m = 3

@@ -299,3 +299,45 @@ def test_workload_parity(smap, name):
         got = ref[idx][: len(want)].cpu().numpy().view(want.dtype)
         assert np.array_equal(got, want), (name, hi)
     assert smap.count(m, n) == math.comb(n + m, m)
+
+
+# ---- EDM (Section 5.1, test 3): float32 against the float64 oracle ----------
+#
+# Tolerance: the kernel computes three float32 differences, their squares,
+# a sum and sqrtf; with each operation rounded to nearest (relative error
+# at most u = 2^-24) the sum of squares is within 5u relative and its
+# square root within 2.5u + the square root's own rounding, at most 3.5u
+# relative, i.e. at most 3.5 ulp of the float32 result (an ulp is at least
+# u times the value); 4 ulp also covers a square root good to 1 ulp.  The
+# diagonal (i = j) is exactly 0.
+EDM_SIZES = [0, 1, 2, 3, 4, 5, 7, 30, 31, 32, 33, 63, 64, 65, 127, 129, 300, 1000]
+EDM_TILES = [32, 16, 64, 128]
+
+
+def _edm_check(got_bits, want, n):
+    got = got_bits.view(np.float32).astype(np.float64)
+    inside = ~np.isnan(want)
+    ulp = np.spacing(want[inside].astype(np.float32)).astype(np.float64)
+    err = np.abs(got[inside] - want[inside])
+    assert (err <= 4 * ulp).all(), (n, float((err / ulp).max()))
+    x1 = np.arange(n + 1)[None, :]
+    x2 = np.arange(n + 1)[:, None]
+    assert (got[(x1 + x2) == n] == 0).all()
+    assert (got_bits.view(np.uint32)[~inside] == si.SENTINEL_U32).all()   # outside never written
+
+
+def test_edm_parity(smap):
+    try:
+        for n in EDM_SIZES:
+            pts = si.points(n, 9000 + n)
+            want = oracle.edm(n, pts)
+            d_pts = torch.from_numpy(pts).cuda()
+            for rho in EDM_TILES:
+                smap.set_tile(2, "edm", rho)
+                for kind in ("h", "bb"):
+                    say(f"edm n={n} rho={rho} {kind}")
+                    d_out = torch.from_numpy(si.sentinel_box(2, n, np.uint32).view(np.int32)).cuda()
+                    launch(smap, kind, 2, n, "edm", d_pts, d_out)
+                    _edm_check(d_out.cpu().numpy().view(np.uint32), want, n)
+    finally:
+        smap.set_tile(2, "edm", 0)
