@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotune result file (read and appended)")
     ap.add_argument("--graph", type=int, default=0,
                     help="time H as replays of a captured graph of this many launches")
+    ap.add_argument("--layout3", default="packed", choices=["packed", "levels"],
+                    help="native layout of the 3-D H map")
     ap.add_argument("--gens", type=int, default=0,
                     help="2-D automaton: time simplex_map_launch_steps advancing this many generations per call")
     ap.add_argument("--op", default=None, choices=["map", "accum", "hash", "hits", "edm"],
@@ -258,6 +260,8 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     useful = smap.count(m, n)
+    if m == 3:
+        smap.set_layout(3, smap.LAYOUT_LEVELS if args.layout3 == "levels" else smap.LAYOUT_PACKED)
 
     log(f"generating {args.workload}: m={m} n={n} op={op}")
     bufs = []
@@ -355,7 +359,7 @@ def main():
         "config": {"workload": f"{args.workload}: m={m} n={n} op={op}", "m": m, "n": n,
                    "op": op, "useful_elements": useful, "rho": info_h["rho"],
                    "beta": info_h["beta"], "autotuned": tuned, "graph_launches": args.graph or None,
-                   "generations_per_call": gens},
+                   "generations_per_call": gens, "layout3": args.layout3 if m == 3 else None},
         "hbm_gbs_algorithmic": achieved,
         "bb": None if bb_ms is None else {
             "ms_per_step": bb_ms, "value": useful * gens / (bb_ms * 1e-3),

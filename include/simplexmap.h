@@ -170,6 +170,23 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
  */
 int simplex_set_tile(int m, int op, int rho, int wg_threads);
 
+/*
+ * Layout of the native part of the 3-D H map for later launches of this
+ * process (H launches, plans and plan info; BB is not affected):
+ *   SMAP_LAYOUT_PACKED (default): the packed grid (N/2) x (N/2) x (N/2 + N/4)
+ *     of Section 4.3, one launch, 1/8 of its workgroups discarded
+ *     (launched / useful tiles of the native part -> 9/8);
+ *   SMAP_LAYOUT_LEVELS: the fully efficient variant of Section 4.3 (one
+ *     parallel space per level of the recursion), realised as the levels'
+ *     ranges concatenated into one launch; level l holds 2^l cubes of side
+ *     N/2^(l+1), every workgroup lands on a tile (launched = useful).
+ * Only m = 3 is accepted (others: SMAP_EINVAL); an unknown layout gives
+ * SMAP_EINVAL.
+ */
+#define SMAP_LAYOUT_PACKED 0
+#define SMAP_LAYOUT_LEVELS 1
+int simplex_set_layout(int m, int layout);
+
 /* ---- autotuning and graphs ------------------------------------------------
  *
  * Theorem 3 (Section 6) frames the choice of the scale and replication

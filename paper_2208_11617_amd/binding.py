@@ -24,7 +24,9 @@ EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_strerror", "simplex_batch_launch", "simplex_serve_run",
            "simplex_autotune", "simplex_autotune_reset", "simplex_graph_create",
            "simplex_graph_launch", "simplex_graph_destroy", "simplex_map_launch_steps",
-           "simplex_bb_launch_steps")
+           "simplex_bb_launch_steps", "simplex_set_layout")
+
+LAYOUT_PACKED, LAYOUT_LEVELS = 0, 1
 
 SERVE_SEQUENTIAL, SERVE_BATCHED = 0, 1
 
@@ -133,6 +135,8 @@ def lib():
     L.simplex_map_launch_steps.restype = ci
     L.simplex_bb_launch_steps.argtypes = [ci, i64, ci, ctypes.c_int32, vp, vp, vp]
     L.simplex_bb_launch_steps.restype = ci
+    L.simplex_set_layout.argtypes = [ci, ci]
+    L.simplex_set_layout.restype = ci
     L.simplex_strerror.argtypes = [ci]
     L.simplex_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -321,3 +325,8 @@ def launch_steps_raw(m, n, op, steps, in_ptr, out_ptr, use_bb=False) -> int:
     if use_bb:
         return L.simplex_bb_launch_steps(m, n, _op(op), steps, in_ptr, out_ptr, None)
     return L.simplex_map_launch_steps(m, n, 0, 0, _op(op), steps, in_ptr, out_ptr, None)
+
+
+def set_layout(m, layout) -> None:
+    """Native layout of the 3-D H map: LAYOUT_PACKED (default) or LAYOUT_LEVELS."""
+    _check(lib().simplex_set_layout(m, layout), "simplex_set_layout")

@@ -116,6 +116,7 @@ struct Plan {
     Divu grid_div[2];            // division by grid[0], grid[1] (set per launch)
     uint32_t nwg;                // grid[0] * grid[1] * grid[2] (< 2^32)
     uint32_t remap;              // 1: renumber workgroups with xcd_remap
+    int32_t layout3;             // m = 3 native part: 0 packed grid, 1 one range per level
 };
 
 // Launch order.  The 8 XCDs of the chip each have their own L2; workgroup L
@@ -221,6 +222,48 @@ SMAP_HD bool h3_native(int j, uint32_t w, int32_t *t)
     return true;
 }
 
+// Level-ordered 3-D map (the fully efficient variant: one range of
+// workgroups per level, here concatenated into one launch).  Level l holds
+// 2^l cubes of side c = N/2^(l+1); the copy index is read in base 2, digit k
+// choosing the corner axis (x_1 or x_2) at recursion depth k, and the cube
+// cells whose local sum is 2c-1 or more are reflected by the hinge onto the
+// x_3 corner, which they cover exactly: every workgroup lands on a tile.
+// The level and the corner offsets have closed forms (no per-level scan).
+SMAP_HD bool h3_levels(const Plan &P, uint32_t w, int32_t *t)
+{
+    // Level l starts at (N^3 - N^3/4^l) / 6 (the sizes N^3/8 4^-l form a
+    // geometric series), so with D = N^3 - 6w the level is the largest l
+    // with D <= 2^(3j - 2l): l = floor((3j - ceil(log2 D)) / 2), one count of
+    // leading zeros.  N^3 <= 2^30 (the planner caps j at 10).
+    const uint32_t j = (uint32_t)P.j;
+    const uint32_t N3 = 1u << (3u * j);
+    const uint32_t D = N3 - 6u * w;              // > N >= 2 for every launched w
+    const uint32_t cl = 32u - (uint32_t)__builtin_clz(D - 1u);   // ceil(log2 D)
+    const uint32_t l = (3u * j - cl) >> 1;
+    const uint32_t start = (N3 - (1u << (3u * j - 2u * l))) / 6u;
+    const uint32_t i = w - start;
+    const uint32_t lc = j - 1u - l;
+    const uint32_t c = 1u << lc;
+    const uint32_t l0 = i & (c - 1u), l1 = (i >> lc) & (c - 1u), l2 = (i >> (2u * lc)) & (c - 1u);
+    // copy q (l binary digits): digit 1 at depth k shifts by N/2^k along x_2,
+    // digit 0 along x_1, so the x_2 offset is q N/2^l and the two offsets
+    // add up to N - N/2^l
+    const uint32_t q = i >> (3u * lc);
+    const int32_t o1 = (int32_t)(q << (j - l));
+    const int32_t o0 = (int32_t)((1u << j) - ((1u << j) >> l)) - o1;
+    const int32_t ci = (int32_t)c;
+    if ((int32_t)(l0 + l1 + l2) >= 2 * ci - 1) {   // hinge onto the x_3 corner
+        t[0] = o0 + ci - 1 - (int32_t)l0;
+        t[1] = o1 + ci - 1 - (int32_t)l1;
+        t[2] = 2 * ci - 1 - (int32_t)l2;
+    } else {
+        t[0] = o0 + (int32_t)l0;
+        t[1] = o1 + (int32_t)l1;
+        t[2] = (int32_t)l2;
+    }
+    return true;
+}
+
 // Level-ordered 4-D map with replication beta (3: hinge, 4: none).
 SMAP_HD bool h4_native(const Plan &P, uint32_t w, int32_t *t)
 {
@@ -293,7 +336,7 @@ SMAP_HD bool decode_h(const Plan &P, uint32_t w, int32_t *t)
     const uint32_t loc = w - pstart;
     if (p == 0) {
         if constexpr (M == 2) { h2_native(P.j, loc, t); return true; }
-        else if constexpr (M == 3) return h3_native(P.j, loc, t);
+        else if constexpr (M == 3) return P.layout3 ? h3_levels(P, loc, t) : h3_native(P.j, loc, t);
         else return h4_native(P, loc, t);
     }
     const int d = m - p;                          // base dimension of this piece

@@ -125,7 +125,8 @@ struct CachedPlan {
     PlanCounts counts;
     int status;
 };
-std::map<std::tuple<int, int64_t, int, int, int, int>, CachedPlan> g_plans;  // (m,n,beta,rho,bb,cls)
+std::map<std::tuple<int, int64_t, int, int, int, int, int>, CachedPlan> g_plans;  // (m,n,beta,rho,bb,cls,layout)
+int g_layout3 = 0;  // H native layout for m = 3 (simplex_set_layout)
 
 TileCfg tile_for(int m, int cls)
 {
@@ -175,11 +176,12 @@ bool box_elems(int m, int64_t n, int64_t *out)
 // Plan of (m, n, beta, tile t, H|BB, op class) from the cache (g_mu held).
 int plan_for(int m, int64_t n, int beta, bool bb, int cls, const TileCfg &t, Plan *P, PlanCounts *C)
 {
-    auto key = std::make_tuple(m, n, bb ? 0 : beta, t.rho, bb ? 1 : 0, cls);
+    const int lay = (m == 3 && !bb) ? g_layout3 : 0;
+    auto key = std::make_tuple(m, n, bb ? 0 : beta, t.rho, bb ? 1 : 0, cls, lay);
     auto it = g_plans.find(key);
     if (it == g_plans.end()) {
         CachedPlan cp{};
-        cp.status = make_plan(m, n, beta, t.rho, bb, &cp.plan, &cp.counts);
+        cp.status = make_plan(m, n, beta, t.rho, bb, &cp.plan, &cp.counts, lay);
         if (cp.status == kOk && !bb && (uint64_t)cp.plan.total * (uint64_t)t.sub > kMaxWorkgroups)
             cp.status = kErange;
         if (cp.status == kOk && bb) {
@@ -1068,6 +1070,14 @@ int simplex_bb_launch_steps(int m, int64_t n, int op, int32_t steps, void *buf_i
                             void *stream)
 {
     return steps_launch(m, n, 0, 0, op, steps, buf_in, buf_out, stream, true);
+}
+
+int simplex_set_layout(int m, int layout)
+{
+    if (m != 3 || (layout != SMAP_LAYOUT_PACKED && layout != SMAP_LAYOUT_LEVELS)) return kEinval;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_layout3 = layout;
+    return kOk;
 }
 
 const char *simplex_strerror(int status)

@@ -42,10 +42,16 @@ inline uint64_t ipow_u64(uint64_t b, int e)
     return r;
 }
 
-// Workgroups of the native d-dim map of T_d(N-1), N = 2^j.
-inline uint64_t native_count(int d, int j, int beta)
+// Workgroups of the native d-dim map of T_d(N-1), N = 2^j (levels: the
+// level-ordered 3-D layout, sum over levels of 2^l c_l^3 = C(N+1, 3)).
+inline uint64_t native_count(int d, int j, int beta, bool levels3 = false)
 {
     if (d == 2) return h2_count(j);
+    if (d == 3 && levels3) {
+        uint64_t s = 0;
+        for (int l = 0; l < j; ++l) s += (uint64_t(1) << l) * ipow_u64(uint64_t(1) << (j - 1 - l), 3);
+        return s;
+    }
     if (d == 3) return h3_count(j);
     uint64_t s = 0;  // d == 4: sum over levels of beta^l c_l^4
     for (int l = 0; l < j; ++l) s += ipow_u64((uint64_t)beta, l) * ipow_u64(uint64_t(1) << (j - 1 - l), 4);
@@ -56,7 +62,7 @@ inline uint64_t native_count(int d, int j, int beta)
 // the 32-bit work-item count of HIP's x dimension.
 constexpr uint64_t kMaxWorkgroups = (uint64_t(1) << 31) / 256;
 
-inline int make_plan(int m, int64_t n, int beta, int rho, bool bb, Plan *P, PlanCounts *C)
+inline int make_plan(int m, int64_t n, int beta, int rho, bool bb, Plan *P, PlanCounts *C, int layout3 = 0)
 {
     if (m < 2 || m > 4 || n < 0 || rho < 1) return kEinval;
     if (n > (int64_t)0x3FFFFFFF) return kErange;
@@ -98,6 +104,17 @@ inline int make_plan(int m, int64_t n, int beta, int rho, bool bb, Plan *P, Plan
         P->L = (int32_t)(P->K - ((1 << j) - 1));
         P->beta = (m == 4) ? beta : 2;
         if (m == 4 && j > 8) return kErange;     // 4*lc shift width and count limits
+        if (m == 3 && layout3) {
+            if (j > 10) return kErange;          // 3*lc shift width
+            P->layout3 = 1;
+            P->nlvl = j;
+            uint64_t acc = 0;
+            for (int l = 0; l < j; ++l) {
+                P->lvl_start[l] = (uint32_t)acc;
+                acc += (uint64_t(1) << l) * ipow_u64(uint64_t(1) << (j - 1 - l), 3);
+            }
+            P->lvl_start[j] = (uint32_t)acc;
+        }
         if (m == 4) {
             P->nlvl = j;
             uint64_t acc = 0;
@@ -107,7 +124,7 @@ inline int make_plan(int m, int64_t n, int beta, int rho, bool bb, Plan *P, Plan
             }
             P->lvl_start[j] = (uint32_t)acc;
         }
-        uint64_t acc = native_count(m, j, beta);
+        uint64_t acc = native_count(m, j, beta, m == 3 && layout3);
         cnt.native = acc;
         P->piece_start[0] = 0;
         P->base_count[0] = (uint32_t)acc;

@@ -341,3 +341,32 @@ def test_edm_parity(smap):
                     _edm_check(d_out.cpu().numpy().view(np.uint32), want, n)
     finally:
         smap.set_tile(2, "edm", 0)
+
+
+def test_levels_layout_3d(smap):
+    """The level-ordered 3-D layout: exactly-once hits and bit-exact CA3."""
+    smap.set_layout(3, smap.LAYOUT_LEVELS)
+    try:
+        for n in _sweep(3):
+            want = to_dev(expected(3, n, "hits", None))
+            for rho in POINT_TILES[3]:
+                smap.set_tile(3, "hits", rho)
+                say(f"levels hits n={n} rho={rho}")
+                d = fresh_out(3, n, "hits")
+                launch(smap, "h", 3, n, "hits", None, d)
+                assert same(d, want), (n, rho)
+        smap.set_tile(3, "hits", 0)
+        for n in [0, 1, 14, 15, 16, 40, 63, 64, 65, 97, 128, 150]:
+            inp = si.box(3, n, "bern", 3500 + n, p=0.25)
+            want = to_dev(expected(3, n, "ca3", inp))
+            d_in = to_dev(inp)
+            for rho, wg in CA3_TILES:
+                smap.set_tile(3, "ca3", rho, wg)
+                say(f"levels ca3 n={n} rho={rho} wg={wg}")
+                d_out = fresh_out(3, n, "ca3")
+                launch(smap, "h", 3, n, "ca3", d_in, d_out)
+                assert same(d_out, want), (n, rho, wg)
+    finally:
+        smap.set_tile(3, "hits", 0)
+        smap.set_tile(3, "ca3", 0)
+        smap.set_layout(3, smap.LAYOUT_PACKED)

@@ -194,3 +194,35 @@ def test_m4_rejects_beta_two():
     with pytest.raises(smap.SimplexMapError) as e:
         smap.plan_info(4, 100, "hits", beta=2)
     assert e.value.status == smap.EUNSUPPORTED
+
+
+def test_levels_layout_3d_covers_exactly_once_without_waste():
+    """The level-ordered 3-D layout (the fully efficient variant of Section
+    4.3): exactly-once coverage for every n and tile, and with no shell the
+    launch is exactly the useful tiles, C(N+1, 3) = (N^3 - N) / 6."""
+    smap.set_layout(3, smap.LAYOUT_LEVELS)
+    try:
+        for op in ("hits", "ca3"):
+            for rho in TILES[(3, op)]:
+                smap.set_tile(3, op, rho)
+                for n in range(0, 131):
+                    check_exact(3, n, op)
+            smap.set_tile(3, op, 0)
+        smap.set_tile(3, "hits", 8)
+        for j in range(1, 9):
+            N = 1 << j
+            info = smap.plan_info(3, 8 * (N - 2), "hits")
+            assert info["native_n"] == N and info["shell_layers"] == 0
+            assert info["launched_tiles"] == info["useful_tiles"] == (N ** 3 - N) // 6
+        # the 3-D workload (n = 1024, rho = 128): fewer launched tiles than packed
+        lev = smap.plan_info(3, 1024, "ca3")
+        smap.set_layout(3, smap.LAYOUT_PACKED)
+        pk = smap.plan_info(3, 1024, "ca3")
+        assert lev["useful_tiles"] == pk["useful_tiles"] and lev["launched_tiles"] < pk["launched_tiles"]
+    finally:
+        smap.set_tile(3, "hits", 0)
+        smap.set_layout(3, smap.LAYOUT_PACKED)
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_layout(2, smap.LAYOUT_LEVELS)
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_layout(3, 7)
