@@ -76,6 +76,52 @@ def time_launches(fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps  # ms per launch
 
 
+def read_power_w():
+    """Socket power of GPU 0 in watts, from amd-smi (a child process), or None."""
+    import subprocess
+    try:
+        r = subprocess.run(["amd-smi", "metric", "--power", "--json"], capture_output=True,
+                           text=True, timeout=10)
+        d = json.loads(r.stdout)
+        return float(d["gpu_data"][0]["power"]["socket_power"]["value"])
+    except Exception:
+        return None
+
+
+def power_leg(fn, seconds, stream):
+    """Run fn(i) back to back for about `seconds` while sampling socket power
+    every ~0.25 s in a thread; returns (launches per second, mean watts,
+    samples)."""
+    import threading
+
+    import torch
+    samples, stop = [], threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            w = read_power_w()
+            if w is not None:
+                samples.append(w)
+            stop.wait(0.25)
+    for i in range(5):
+        fn(i)
+    torch.cuda.synchronize()
+    th = threading.Thread(target=sampler, daemon=True)
+    t0 = time.perf_counter()
+    th.start()
+    count = 0
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(50):
+            fn(count)
+            count += 1
+        torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stop.set()
+    th.join()
+    steady = samples[1:] if len(samples) > 2 else samples     # drop the ramp-up sample
+    return count / dt, (sum(steady) / len(steady)) if steady else None, len(samples)
+
+
 def copy_probe(nbytes, steps, stream):
     """A plain streaming kernel over ``nbytes`` (torch's elementwise
     bitwise_not on uint8: one read and one write per byte, like a copy, but
@@ -221,6 +267,8 @@ def main():
     ap.add_argument("--no-bb", action="store_true", help="skip timing the BB baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the plain-copy probe")
     ap.add_argument("--beta", type=int, default=0)
+    ap.add_argument("--power", type=float, default=0.0,
+                    help="also run H and BB for this many seconds each while sampling socket power (amd-smi)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick rho / workgroup size / beta for the H launch by timing first")
     ap.add_argument("--tune-cache", default=None, help="autotune result file (read and appended)")
@@ -331,6 +379,18 @@ def main():
         else:
             bb_ms = time_launches(step_fn(smap.bb_launch), args.steps, args.warmup, stream)
 
+    power = None
+    if args.power > 0:
+        log(f"power legs: {args.power} s each")
+        idle = read_power_w()
+        h_rate, h_w, h_n = power_leg(step_fn(h_launch), args.power, stream)
+        power = {"idle_w": idle, "h": {"launches_per_s": h_rate, "watts": h_w, "samples": h_n,
+                                       "elements_per_joule": None if not h_w else useful * gens * h_rate / h_w}}
+        if not args.no_bb and args.gens == 0 and args.graph == 0:
+            b_rate, b_w, b_n = power_leg(step_fn(smap.bb_launch), args.power, stream)
+            power["bb"] = {"launches_per_s": b_rate, "watts": b_w, "samples": b_n,
+                           "elements_per_joule": None if not b_w else useful * b_rate / b_w}
+
     copy = None
     if not args.no_copy:
         log("timing a plain copy of the same byte count")
@@ -382,6 +442,7 @@ def main():
             "frac_of_copy": None if copy is None else achieved / copy["gbs"],
         },
         "copy": copy,
+        "power": power,
         "cpu_baseline": None,
     }
     if op == "map":
