@@ -143,7 +143,8 @@ def bench_serve(args):
     with n log-uniform in [64, 4096], 40 % m = 3 with n log-uniform in
     [32, 512]), inputs resident in HBM, outputs in an arena of --budget-gib.
     Saturated throughput (every job at t = 0) of sequential plain-H launches
-    and of continuous batching, then both at a Poisson load of --load times
+    and of continuous batching (batched launches, and persistent work-queue
+    launches), then all three at a Poisson load of --load times
     the sequential saturated rate, with p50/p99 latency (arrival to the end
     of the job's launch, device events)."""
     import math
@@ -176,15 +177,17 @@ def bench_serve(args):
                 "mean_ms": float(lat.mean() * 1e3), "launches": int(max(r["batch"] for r in recs)) + 1,
                 "makespan_s": span}
 
+    modes = (("sequential", smap.SERVE_SEQUENTIAL), ("batched", smap.SERVE_BATCHED),
+             ("persistent", smap.SERVE_PERSISTENT))
     res = {}
-    for name, mode in (("sequential", smap.SERVE_SEQUENTIAL), ("batched", smap.SERVE_BATCHED)):
+    for name, mode in modes:
         for _ in range(args.warmup_replays):
             replay(jobs0, mode)
         log(f"saturated replay: {name}")
         res[f"saturated_{name}"] = replay(jobs0, mode)
     rate = args.load * res["saturated_sequential"]["jobs_per_s"]
     trace = si.serve_trace(args.jobs, rate)
-    for name, mode in (("sequential", smap.SERVE_SEQUENTIAL), ("batched", smap.SERVE_BATCHED)):
+    for name, mode in modes:
         log(f"Poisson replay at {rate:.0f} jobs/s: {name}")
         res[f"load_{name}"] = replay(trace, mode)
     sat_b = res["saturated_batched"]
@@ -207,6 +210,8 @@ def bench_serve(args):
                    "offered_rate_jobs_per_s": rate, "max_inflight": args.max_inflight},
         "serving": res,
         "batched_vs_sequential_saturated": sat_b["jobs_per_s"] / res["saturated_sequential"]["jobs_per_s"],
+        "persistent_vs_sequential_saturated":
+            res["saturated_persistent"]["jobs_per_s"] / res["saturated_sequential"]["jobs_per_s"],
         "roofline": None,
         "cpu_baseline": None,
     }

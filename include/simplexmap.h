@@ -318,6 +318,33 @@ struct simplex_job {
  */
 int simplex_batch_launch(const struct simplex_job *jobs, int32_t njobs, void *stream);
 
+/*
+ * Steps every job of `jobs[0..njobs)` with the H map in ONE persistent
+ * launch for all classes (CA2 and CA3 jobs mixed), through a device-side
+ * work queue of H-mapped block ranges.  A work unit is one H-mapped tile
+ * (CA2, rho = 256) or one of the 4 sub-blocks of an H-mapped tile (CA3,
+ * rho = 64); the units of all jobs are concatenated, job after job.  The
+ * grid holds only as many workgroups (256 threads) as the device runs at
+ * once — occupancy times compute units, or max_workgroups if that is
+ * smaller and non-zero — and each workgroup claims unit after unit with an
+ * atomic add on a head counter in device memory, until the head reaches
+ * the tail (the unit count, fixed at launch); a claimed unit is mapped to
+ * its job by a binary search over the unit prefix sums and decoded with
+ * the job's own H plan (Section 4; the blocks of a job's reduced grid are
+ * the units).  Outputs equal those of simplex_map_launch for each job
+ * alone.
+ *
+ * Tables (head counter, prefix sums, jobs) come from the same ring as
+ * simplex_batch_launch's and travel with an asynchronous copy on `stream`;
+ * the call returns without synchronising.  Up to 4096 jobs go in one
+ * launch (more are split over several launches).  max_workgroups: 0 for
+ * the device's resident count, or a smaller positive cap (a cap of 1 runs
+ * every unit on one workgroup).  Errors are those of simplex_batch_launch,
+ * plus SMAP_EINVAL for max_workgroups < 0.
+ */
+int simplex_queue_launch(const struct simplex_job *jobs, int32_t njobs, int32_t max_workgroups,
+                         void *stream);
+
 /* ---- serving loop -------------------------------------------------------
  *
  * A request stream of automaton-step jobs (the continuous-batching serving
@@ -349,6 +376,7 @@ struct simplex_serve_record {
 
 #define SMAP_SERVE_SEQUENTIAL 0  /* one simplex_map_launch per job, in arrival order */
 #define SMAP_SERVE_BATCHED 1     /* continuous batching with simplex_batch_launch */
+#define SMAP_SERVE_PERSISTENT 2  /* continuous batching with simplex_queue_launch */
 
 /*
  * Replays `jobs` in real time on the current device and returns when every
@@ -366,7 +394,10 @@ struct simplex_serve_record {
  * jobs go out as one simplex_batch_launch.  Batches alternate between two
  * streams of the default priority (created and destroyed by the call), so
  * consecutive batches overlap on the device.  Jobs that arrive while
- * others run join the next batch.  Before the clock starts, one tiny step
+ * others run join the next batch.
+ * SMAP_SERVE_PERSISTENT: as SMAP_SERVE_BATCHED, but each batch goes out as
+ * one simplex_queue_launch (all classes in one persistent launch).
+ * Before the clock starts, one tiny step
  * of each class runs on every stream of the loop (a kernel's first launch
  * in a process otherwise pays for loading its code object), on 16 KiB of
  * zeroed device memory the library keeps with its job tables (never on the

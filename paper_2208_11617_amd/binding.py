@@ -24,11 +24,11 @@ EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_strerror", "simplex_batch_launch", "simplex_serve_run",
            "simplex_autotune", "simplex_autotune_reset", "simplex_graph_create",
            "simplex_graph_launch", "simplex_graph_destroy", "simplex_map_launch_steps",
-           "simplex_bb_launch_steps", "simplex_set_layout")
+           "simplex_bb_launch_steps", "simplex_set_layout", "simplex_queue_launch")
 
 LAYOUT_PACKED, LAYOUT_LEVELS = 0, 1
 
-SERVE_SEQUENTIAL, SERVE_BATCHED = 0, 1
+SERVE_SEQUENTIAL, SERVE_BATCHED, SERVE_PERSISTENT = 0, 1, 2
 
 
 class SimplexMapError(RuntimeError):
@@ -117,6 +117,8 @@ def lib():
     L.simplex_set_tile.restype = ci
     L.simplex_batch_launch.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, vp]
     L.simplex_batch_launch.restype = ci
+    L.simplex_queue_launch.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_int32, vp]
+    L.simplex_queue_launch.restype = ci
     L.simplex_serve_run.argtypes = [ctypes.POINTER(ServeJob), ctypes.c_int32, vp, u64, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ServeRecord)]
     L.simplex_serve_run.restype = ci
@@ -240,6 +242,20 @@ def batch_launch(jobs, stream=None) -> None:
     """One step of every (m, op, n, buf_in, buf_out) job, batched by class."""
     arr = _job_array(jobs)
     _check(lib().simplex_batch_launch(arr, len(jobs), _stream(stream)), "simplex_batch_launch")
+
+
+def queue_launch_raw(jobs, njobs=None, max_workgroups=0, stream_ptr=None) -> int:
+    """Status-returning persistent work-queue launch (jobs as for batch_launch)."""
+    arr = _job_array(jobs)
+    return lib().simplex_queue_launch(arr, len(jobs) if njobs is None else njobs, max_workgroups, stream_ptr)
+
+
+def queue_launch(jobs, max_workgroups=0, stream=None) -> None:
+    """One step of every (m, op, n, buf_in, buf_out) job in one persistent
+    launch that pulls H-mapped block ranges from a device-side work queue."""
+    arr = _job_array(jobs)
+    _check(lib().simplex_queue_launch(arr, len(jobs), max_workgroups, _stream(stream)),
+           "simplex_queue_launch")
 
 
 def serve_run_raw(jobs, arena_ptr, arena_bytes, mode, max_inflight=4, keep_outputs=False):

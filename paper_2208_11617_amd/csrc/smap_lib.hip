@@ -562,6 +562,27 @@ int launch_batch_chunk(BatchRing &R, int kind, const BatchItem *items, int cnt, 
     return kOk;
 }
 
+// Workgroups of the queue kernel the device holds at once (occupancy times
+// compute units), per device.
+std::map<int, uint32_t> g_queue_grid;
+
+int queue_grid_for_device(uint32_t *grid)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kEhip;
+    auto it = g_queue_grid.find(dev);
+    if (it == g_queue_grid.end()) {
+        int cus = 0, occ = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return kEhip;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(&k_queue),
+                                                         kQueueThreads, 0) != hipSuccess)
+            return kEhip;
+        it = g_queue_grid.emplace(dev, (uint32_t)std::max(1, cus * std::max(1, occ))).first;
+    }
+    *grid = it->second;
+    return kOk;
+}
+
 // Load the batched kernels' code and allocate the table ring before the
 // first batch (both take milliseconds on first use).
 int batch_prepare()
@@ -572,13 +593,17 @@ int batch_prepare()
         reinterpret_cast<const void *>(&k_ca2_batch<256, 4, 16, 2, true>),
         reinterpret_cast<const void *>(&k_ca3_batch<64, kBatchCa3Ry, kBatchCa3Rz, kBatchCa3Rl, false>),
         reinterpret_cast<const void *>(&k_ca3_batch<64, kBatchCa3Ry, kBatchCa3Rz, kBatchCa3Rl, true>),
+        reinterpret_cast<const void *>(&k_queue),
     };
     for (const void *f : fns) {
         if (hipFuncGetAttributes(&a, f) != hipSuccess) return kEhip;
     }
     std::lock_guard<std::mutex> lk(g_batch_mu);   // and allocate the table ring now
     BatchRing *R = nullptr;
-    return ring_for_device(&R);
+    const int rc = ring_for_device(&R);
+    if (rc != kOk) return rc;
+    uint32_t grid = 0;
+    return queue_grid_for_device(&grid);
 }
 
 // The warm-up buffers of this device (allocated with the ring).
@@ -629,6 +654,115 @@ int batch_launch(const simplex_job *jobs, int32_t njobs, void *stream)
             rc = launch_batch_chunk(*R, kind, v.data() + o, cnt, s);
             if (rc != kOk) return rc;
         }
+    }
+    return kOk;
+}
+
+// ---- persistent work-queue launch -----------------------------------------
+
+// One persistent launch over items[0..cnt) (mixed kinds): ring bytes hold
+// the head counter (zero), the unit prefix sums and the job array.
+int launch_queue_chunk(BatchRing &R, const BatchItem *items, const uint32_t *kinds, int cnt, uint32_t max_wg,
+                       hipStream_t s)
+{
+    constexpr size_t head_bytes = 256;
+    const size_t start_bytes = ((sizeof(uint32_t) * (size_t)(cnt + 1) + 255) / 256) * 256;
+    const size_t bytes = ((head_bytes + start_bytes + sizeof(QueueJob) * (size_t)cnt + 255) / 256) * 256;
+    uint64_t acc = 0;
+    for (int i = 0; i < cnt; ++i) acc += items[i].nwg;
+    if (acc == 0) return kOk;
+    if (acc > kMaxWorkgroups) return kErange;
+    uint32_t grid = 0;
+    int rc = queue_grid_for_device(&grid);
+    if (rc != kOk) return rc;
+    if (max_wg > 0) grid = std::min(grid, max_wg);
+    grid = (uint32_t)std::min<uint64_t>(grid, acc);
+    size_t off = 0;
+    rc = ring_reserve(R, bytes, &off);
+    if (rc != kOk) return rc;
+    uint8_t *h = R.host + off;
+    uint8_t *d = R.dev + off;
+    std::memset(h, 0, head_bytes);
+    uint32_t *start = reinterpret_cast<uint32_t *>(h + head_bytes);
+    QueueJob *jobs = reinterpret_cast<QueueJob *>(h + head_bytes + start_bytes);
+    acc = 0;
+    for (int i = 0; i < cnt; ++i) {
+        start[i] = (uint32_t)acc;
+        jobs[i].P = items[i].P;
+        jobs[i].in = items[i].in;
+        jobs[i].out = items[i].out;
+        jobs[i].kind = kinds[i];
+        jobs[i].reserved = 0;
+        acc += items[i].nwg;
+    }
+    start[cnt] = (uint32_t)acc;
+    if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return kEhip;
+    hipLaunchKernelGGL(k_queue, dim3(grid), dim3(kQueueThreads), 0, s, reinterpret_cast<uint32_t *>(d),
+                       reinterpret_cast<const uint32_t *>(d + head_bytes),
+                       reinterpret_cast<const QueueJob *>(d + head_bytes + start_bytes), (uint32_t)cnt,
+                       (uint32_t)acc);
+    if (hipGetLastError() != hipSuccess) return kEhip;
+    hipEvent_t ev = nullptr;
+    if (!R.spare.empty()) {
+        ev = R.spare.back();
+        R.spare.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        return kEhip;
+    }
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        R.spare.push_back(ev);
+        return kEhip;
+    }
+    R.used.push_back(BatchRing::Use{off, off + bytes, ev});
+    R.head = off + bytes;
+    return kOk;
+}
+
+int queue_launch(const simplex_job *jobs, int32_t njobs, int32_t max_wg, void *stream)
+{
+    if (njobs < 0 || (njobs > 0 && !jobs) || max_wg < 0) return kEinval;
+    if (njobs == 0) return kOk;
+    constexpr TileCfg kQ2 = {kQueueCa2Rho, kQueueThreads, 1};
+    constexpr TileCfg kQ3 = {kQueueCa3Rho, kQueueThreads,
+                             (kQueueCa3Rho / kQueueCa3Ry) * (kQueueCa3Rho / kQueueCa3Rz)};
+    static_assert(Ca2Walk<kQueueCa2Rho, kQueueCa2W, kQueueCa2R>::SUB == kQ2.sub &&
+                  Ca3Walk<kQueueCa3Rho, kQueueCa3Ry, kQueueCa3Rz, kQueueCa3Rl>::SUB == kQ3.sub,
+                  "queue tile configurations disagree with the kernel");
+    std::vector<BatchItem> items;
+    std::vector<uint32_t> kinds;
+    items.reserve((size_t)njobs);
+    kinds.reserve((size_t)njobs);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (int32_t i = 0; i < njobs; ++i) {
+            const simplex_job &J = jobs[i];
+            const bool ca2 = J.m == 2 && J.op == OP_CA2, ca3 = J.m == 3 && J.op == OP_CA3;
+            if (!ca2 && !ca3) return kEinval;
+            int rc = check_op(J.m, J.n, J.op);
+            if (rc != kOk) return rc;
+            rc = check_buffers(J.m, J.n, J.op, J.buf_in, J.buf_out);
+            if (rc != kOk) return rc;
+            const TileCfg &t = ca2 ? kQ2 : kQ3;
+            BatchItem it{};
+            rc = plan_for(J.m, J.n, 2, false, ca2 ? 1 : 2, t, &it.P, nullptr);
+            if (rc != kOk) return rc;
+            it.in = (const uint8_t *)J.buf_in;
+            it.out = (uint8_t *)J.buf_out;
+            const bool small = J.n < kQueueSmallN;
+            it.nwg = small ? 1u : it.P.total * (uint32_t)t.sub;   // a small job is one unit
+            items.push_back(it);
+            kinds.push_back(small ? (ca2 ? kQueueCa2Small : kQueueCa3Small) : (ca2 ? kQueueCa2 : kQueueCa3));
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchRing *R = nullptr;
+    int rc = ring_for_device(&R);
+    if (rc != kOk) return rc;
+    for (size_t o = 0; o < items.size(); o += kBatchMaxJobs) {
+        const int cnt = (int)std::min<size_t>(kBatchMaxJobs, items.size() - o);
+        rc = launch_queue_chunk(*R, items.data() + o, kinds.data() + o, cnt, (uint32_t)max_wg,
+                                (hipStream_t)stream);
+        if (rc != kOk) return rc;
     }
     return kOk;
 }
@@ -985,13 +1119,19 @@ int simplex_batch_launch(const struct simplex_job *jobs, int32_t njobs, void *st
     return batch_launch(jobs, njobs, stream);
 }
 
+int simplex_queue_launch(const struct simplex_job *jobs, int32_t njobs, int32_t max_workgroups, void *stream)
+{
+    return queue_launch(jobs, njobs, max_workgroups, stream);
+}
+
 int simplex_serve_run(const struct simplex_serve_job *jobs, int32_t njobs, void *arena,
                       uint64_t arena_bytes, int32_t mode, int32_t max_inflight, int32_t keep_outputs,
                       struct simplex_serve_record *records)
 {
     if (njobs < 0 || (njobs > 0 && (!jobs || !arena))) return kEinval;
-    if (mode != SMAP_SERVE_SEQUENTIAL && mode != SMAP_SERVE_BATCHED) return kEinval;
-    if (mode == SMAP_SERVE_BATCHED && max_inflight < 1) return kEinval;
+    if (mode != SMAP_SERVE_SEQUENTIAL && mode != SMAP_SERVE_BATCHED && mode != SMAP_SERVE_PERSISTENT)
+        return kEinval;
+    if (mode != SMAP_SERVE_SEQUENTIAL && max_inflight < 1) return kEinval;
     uint64_t need_all = 0;
     for (int32_t i = 0; i < njobs; ++i) {
         const simplex_serve_job &J = jobs[i];
@@ -1012,7 +1152,7 @@ int simplex_serve_run(const struct simplex_serve_job *jobs, int32_t njobs, void 
         records = local.data();
     }
     for (int32_t i = 0; i < njobs; ++i) records[i] = simplex_serve_record{-1.0, -1.0, -1.0, -1.0, 0, -1, kOk};
-    if (mode == SMAP_SERVE_BATCHED) {
+    if (mode != SMAP_SERVE_SEQUENTIAL) {
         const int rc = batch_prepare();
         if (rc != kOk) return rc;
     }

@@ -6,8 +6,9 @@
 // here by a first-fit allocator), and are launched either one by one with
 // the H map (the sequential baseline) or in continuous batches: whenever
 // fewer than `max_inflight` batches are running, every admitted job that
-// has not been launched goes out as one batched launch, alternating
-// between two streams so that consecutive batches overlap on the device.
+// has not been launched goes out as one batched launch (or as one
+// persistent work-queue launch), alternating between two streams so that
+// consecutive batches overlap on the device.
 // Completion times come from device events, so a job's latency is the
 // time from its arrival to the end of the launch that ran it.
 #pragma once
@@ -83,7 +84,11 @@ inline int serve_run(const simplex_serve_job *jobs, int32_t njobs, uint8_t *aren
         hipEvent_t ev;
         std::vector<int32_t> jobs;
     };
-    const int nstreams = mode == SMAP_SERVE_BATCHED ? 2 : 1;
+    const int nstreams = mode == SMAP_SERVE_SEQUENTIAL ? 1 : 2;
+    // a group of admitted jobs goes out as one launch group of the mode
+    auto launch_group = [&](const simplex_job *b, int32_t cnt, hipStream_t s) {
+        return mode == SMAP_SERVE_PERSISTENT ? simplex_queue_launch(b, cnt, 0, s) : simplex_batch_launch(b, cnt, s);
+    };
     hipStream_t streams[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> pool;  // events ready for reuse
     std::deque<Flight> flying[2];  // per stream, in issue order
@@ -112,9 +117,9 @@ inline int serve_run(const simplex_serve_job *jobs, int32_t njobs, uint8_t *aren
                                    {3, SMAP_OP_CA3, 15, warm, warm + 8192}};
         for (int i = 0; i < nstreams && status == SMAP_OK; ++i) {
             for (const simplex_job &w : wj) {
-                const int rc = mode == SMAP_SERVE_BATCHED
-                                   ? simplex_batch_launch(&w, 1, streams[i])
-                                   : simplex_map_launch(w.m, w.n, 0, 0, w.op, w.buf_in, w.buf_out, streams[i]);
+                const int rc = mode == SMAP_SERVE_SEQUENTIAL
+                                   ? simplex_map_launch(w.m, w.n, 0, 0, w.op, w.buf_in, w.buf_out, streams[i])
+                                   : launch_group(&w, 1, streams[i]);
                 if (rc != SMAP_OK) status = rc;
             }
             if (status == SMAP_OK && hipStreamSynchronize(streams[i]) != hipSuccess) status = SMAP_EHIP;
@@ -206,7 +211,7 @@ inline int serve_run(const simplex_serve_job *jobs, int32_t njobs, uint8_t *aren
             }
             Flight f;
             if (!get_event(&f.ev)) { status = SMAP_EHIP; break; }
-            const int rc = simplex_batch_launch(batch.data(), (int32_t)batch.size(), streams[si]);
+            const int rc = launch_group(batch.data(), (int32_t)batch.size(), streams[si]);
             for (int32_t j : admitted) rec[j].status = rc;
             if (rc != SMAP_OK) { status = rc; pool.push_back(f.ev); break; }
             if (hipEventRecord(f.ev, streams[si]) != hipSuccess) { status = SMAP_EHIP; break; }

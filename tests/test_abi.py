@@ -146,6 +146,22 @@ def test_batch_launch_argument_errors():
     assert smap.batch_launch_raw([good, (2, "ca2", 100, 4096, 4096 + 50)]) == E  # overlap
 
 
+def test_queue_launch_argument_errors():
+    """simplex_queue_launch validates every job and the workgroup cap first."""
+    E = smap.EINVAL
+    assert smap.queue_launch_raw([], 0) == smap.OK            # empty batch: no-op
+    assert smap.queue_launch_raw([], -1) == E
+    assert smap.lib().simplex_queue_launch(None, 3, 0, None) == E
+    good = (2, "ca2", 100, 4096, 1 << 20)
+    assert smap.queue_launch_raw([good], max_workgroups=-1) == E
+    assert smap.queue_launch_raw([(2, "ca3", 10, 4096, 1 << 20)]) == E   # CA3 needs m = 3
+    assert smap.queue_launch_raw([(3, "ca2", 10, 4096, 1 << 20)]) == E
+    assert smap.queue_launch_raw([(3, "hash", 10, 4096, 1 << 20)]) == E  # automata only
+    assert smap.queue_launch_raw([good, (3, "ca3", -1, 4096, 1 << 20)]) == E
+    assert smap.queue_launch_raw([good, (2, "ca2", 100, 4096, 0)]) == E  # NULL output
+    assert smap.queue_launch_raw([good, (2, "ca2", 100, 4096, 4096 + 50)]) == E  # overlap
+
+
 def test_serve_run_argument_errors():
     """simplex_serve_run validates the whole job stream before any work."""
     E = smap.EINVAL
@@ -154,6 +170,7 @@ def test_serve_run_argument_errors():
     job = (2, "ca2", 100, 4096, 0.0)
     assert smap.serve_run_raw([job], arena, size, 7)[0] == E                    # bad mode
     assert smap.serve_run_raw([job], arena, size, smap.SERVE_BATCHED, 0)[0] == E  # max_inflight
+    assert smap.serve_run_raw([job], arena, size, smap.SERVE_PERSISTENT, 0)[0] == E
     assert smap.serve_run_raw([job], 0, size, smap.SERVE_BATCHED)[0] == E       # no arena
     assert smap.serve_run_raw([(2, "ca2", 100, 4096, 1.0), (2, "ca2", 100, 4096, 0.5)],
                               arena, size, smap.SERVE_BATCHED)[0] == E          # arrivals out of order

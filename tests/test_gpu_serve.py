@@ -82,6 +82,60 @@ def test_batch_many_jobs_split_over_launches(smap):
     assert torch.equal(stacked, ref.unsqueeze(0).expand_as(stacked))
 
 
+@pytest.mark.parametrize("cap", [0, 1, 7])
+def test_queue_matches_single_launch_and_oracle(smap, cap):
+    """One persistent launch over the mixed classes: cap 0 runs the device's
+    resident workgroup count, 1 runs every unit on one workgroup, 7 makes
+    workgroups claim units of several jobs and classes in turn."""
+    ins, refs, outs = [], [], []
+    for k, (m, n) in enumerate(MIX):
+        inp = job_input(m, n, 5400 + k)
+        ins.append(inp)
+        refs.append(alone(smap, m, n, inp))
+        outs.append(si.sentinel_box_torch(m, n, True, device="cuda"))
+    torch.cuda.synchronize()
+    order = list(range(len(MIX)))
+    np.random.default_rng(8).shuffle(order)
+    say(f"queue launch of {len(order)} jobs, cap {cap}")
+    smap.queue_launch([(MIX[i][0], OP[MIX[i][0]], MIX[i][1], ins[i], outs[i]) for i in order],
+                      max_workgroups=cap)
+    torch.cuda.synchronize()
+    for k, (m, n) in enumerate(MIX):
+        say(f"compare m={m} n={n}")
+        assert torch.equal(outs[k], refs[k]), (m, n)
+        if (m == 2 and n <= 300) or (m == 3 and n <= 40):
+            want = si.sentinel_box(m, n, np.uint8)
+            oracle.apply(m, n, OP[m], ins[k].cpu().numpy(), want)
+            assert np.array_equal(outs[k].cpu().numpy(), want), (m, n)
+
+
+def test_queue_large_jobs_and_split(smap):
+    """A large job of each class beside small ones, repeated launches
+    reusing the ring, and more jobs than one launch takes (4096)."""
+    big = [(2, 5000), (3, 300), (2, 20), (3, 17)]
+    ins = [job_input(m, n, 5500 + k) for k, (m, n) in enumerate(big)]
+    refs = [alone(smap, m, n, ins[k]) for k, (m, n) in enumerate(big)]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        outs = [si.sentinel_box_torch(m, n, True, device="cuda") for m, n in big]
+        say(f"queue launch of large jobs, repeat {rep}")
+        smap.queue_launch([(m, OP[m], n, ins[k], outs[k]) for k, (m, n) in enumerate(big)])
+        torch.cuda.synchronize()
+        for k, (m, n) in enumerate(big):
+            assert torch.equal(outs[k], refs[k]), (rep, m, n)
+    n = 20
+    outs = [si.sentinel_box_torch(3, n, True, device="cuda") for _ in range(4100)]
+    torch.cuda.synchronize()
+    say("queue launch of 4100 jobs")
+    inp = job_input(3, n, 5601)
+    ref = alone(smap, 3, n, inp)
+    torch.cuda.synchronize()
+    smap.queue_launch([(3, "ca3", n, inp, o) for o in outs])
+    torch.cuda.synchronize()
+    stacked = torch.stack(outs)
+    assert torch.equal(stacked, ref.unsqueeze(0).expand_as(stacked))
+
+
 def serve_jobs(count, seed, spread_s):
     rng = np.random.default_rng(seed)
     jobs = []
@@ -96,7 +150,7 @@ def serve_jobs(count, seed, spread_s):
     return jobs
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_serve_results_same_alone_and_in_the_mix(smap, mode):
     spec = serve_jobs(40, 11, 0.02)
     ins = [job_input(m, n, 6000 + k) for k, (m, n, _) in enumerate(spec)]
@@ -115,7 +169,7 @@ def test_serve_results_same_alone_and_in_the_mix(smap, mode):
         box = (n + 1) ** m
         got = arena[r["out_offset"]:r["out_offset"] + box].view((n + 1,) * m)
         assert torch.equal(got, refs[k]), (k, m, n)
-    if mode == 1:
+    if mode in (1, 2):
         assert max(r["batch"] for r in recs) < len(spec)      # some jobs shared a launch
     else:
         assert sorted(r["batch"] for r in recs) == list(range(len(spec)))
@@ -131,7 +185,7 @@ def test_serve_small_budget_queues_and_completes(smap):
     ref_last = alone(smap, 2, n, ins[-1])
     arena = torch.full((2 * size,), 0xA5, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         say(f"small budget mode={mode}")
         recs = smap.serve_run([(2, "ca2", n, ins[k], 0.0) for k in range(count)], arena, mode)
         assert all(r["status"] == smap.OK for r in recs)
