@@ -61,19 +61,66 @@ def stored_traffic(workload: str, op: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def time_launches(fn, steps, warmup, stream):
+def time_launches(fn, steps, warmup, stream, stats=None, batches=10):
+    """Mean ms per launch over `steps` back-to-back launches (HIP events on
+    `stream`).  With a dict `stats`, events between `batches` equal batches
+    of the same timed region also give the median, mean and standard error
+    of the per-batch means (ms per launch)."""
     import torch
     for i in range(warmup):
         fn(i)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for i in range(steps):
-        fn(warmup + i)
-    end.record(stream)
+    nb = max(1, min(batches, steps)) if stats is not None else 1
+    cuts = [round(k * steps / nb) for k in range(nb + 1)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nb + 1)]
+    evs[0].record(stream)
+    for b in range(nb):
+        for i in range(cuts[b], cuts[b + 1]):
+            fn(warmup + i)
+        evs[b + 1].record(stream)
     torch.cuda.synchronize()
-    return start.elapsed_time(end) / steps  # ms per launch
+    if stats is not None:
+        per = sorted(evs[b].elapsed_time(evs[b + 1]) / (cuts[b + 1] - cuts[b]) for b in range(nb))
+        mean = sum(per) / nb
+        sem = (sum((x - mean) ** 2 for x in per) / (nb - 1) / nb) ** 0.5 if nb > 1 else None
+        mid = per[nb // 2] if nb % 2 else 0.5 * (per[nb // 2 - 1] + per[nb // 2])
+        stats.update(batches=nb, median_ms=mid, mean_ms=mean, sem_ms=sem,
+                     sem_rel=None if sem is None else sem / mean)
+    return evs[0].elapsed_time(evs[-1]) / steps  # ms per launch
+
+
+def tile_sweep(m, op, fn_for, steps, warmup, stream):
+    """H and BB at every compiled (rho, workgroup size) of the op class, each
+    pair with the same tile (same-shape); returns the list of timings."""
+    from paper_2208_11617_amd import binding as smap
+    rows = []
+    smap.autotune_reset()   # H launches follow set_tile only without a tuned choice
+    try:
+        for rho in (4, 8, 16, 32, 64, 128, 256, 512, 1024):
+            for wg in (64, 128, 256, 512):
+                try:
+                    smap.set_tile(m, op, rho, wg)
+                except smap.SimplexMapError:
+                    continue   # not compiled for this class
+                row = {"rho": rho, "wg_threads": wg}
+                for name, launch in (("h", smap.map_launch), ("bb", smap.bb_launch)):
+                    try:
+                        row[f"{name}_ms"] = time_launches(fn_for(launch), steps, warmup, stream)
+                    except smap.SimplexMapError:
+                        row[f"{name}_ms"] = None   # beyond the grid limits
+                rows.append(row)
+    finally:
+        smap.set_tile(m, op, 0)
+    return rows
+
+
+def best_vs_best(rows):
+    """The fastest H and the fastest BB of a tile sweep, each tuned on its own."""
+    h = min((r for r in rows if r["h_ms"] is not None), key=lambda r: r["h_ms"])
+    b = min((r for r in rows if r["bb_ms"] is not None), key=lambda r: r["bb_ms"])
+    return {"h": {"rho": h["rho"], "wg_threads": h["wg_threads"], "ms_per_step": h["h_ms"]},
+            "bb": {"rho": b["rho"], "wg_threads": b["wg_threads"], "ms_per_step": b["bb_ms"]},
+            "h_vs_bb_speedup": b["bb_ms"] / h["h_ms"], "same_shape": rows}
 
 
 def read_power_w():
@@ -282,7 +329,9 @@ def main():
     ap.add_argument("--layout3", default="packed", choices=["packed", "levels"],
                     help="native layout of the 3-D H map")
     ap.add_argument("--gens", type=int, default=0,
-                    help="2-D automaton: time simplex_map_launch_steps advancing this many generations per call")
+                    help="automata: time simplex_map_launch_steps advancing this many generations per call")
+    ap.add_argument("--best-vs-best", action="store_true",
+                    help="also time H and BB at every compiled tile: same-shape pairs and best vs best")
     ap.add_argument("--op", default=None, choices=["map", "accum", "hash", "hits", "edm"],
                     help="run this per-element op on the workload's m and n instead of its own")
     args = ap.parse_args()
@@ -350,11 +399,12 @@ def main():
     h_launch = lambda *a, **k: smap.map_launch(*a, beta=args.beta, **k)  # noqa: E731
     gens = 1
     if args.gens > 0:
-        if op != "ca2":
-            raise SystemExit("--gens applies to the 2-D automaton (workload c2)")
+        if op not in ("ca2", "ca3"):
+            raise SystemExit("--gens applies to the automata (workloads c2 and c3)")
         gens = args.gens
         h_launch = lambda m_, n_, op_, s_, d_, stream=None: smap.map_launch_steps(  # noqa: E731
             m_, n_, op_, gens, s_, d_, beta=args.beta, stream=stream)
+    h_stats, bb_stats = {}, {}
     if args.graph > 0:
         # one replay = args.graph launches (automata: ping-pong, pointwise: repeated)
         K = args.graph if not u8 else args.graph + (args.graph % 2)
@@ -371,7 +421,7 @@ def main():
         h_ms = graph_ms(False)
     else:
         log(f"timing H: {args.warmup} warmup + {args.steps} steps")
-        h_ms = time_launches(step_fn(h_launch), args.steps, args.warmup, stream)
+        h_ms = time_launches(step_fn(h_launch), args.steps, args.warmup, stream, stats=h_stats)
     bb_ms = None
     if not args.no_bb:
         log("timing BB" + (" as graph replays" if args.graph > 0 else ""))
@@ -382,7 +432,11 @@ def main():
                 m_, n_, op_, gens, s_, d_, stream=stream)
             bb_ms = time_launches(step_fn(bb_steps), args.steps, args.warmup, stream)
         else:
-            bb_ms = time_launches(step_fn(smap.bb_launch), args.steps, args.warmup, stream)
+            bb_ms = time_launches(step_fn(smap.bb_launch), args.steps, args.warmup, stream, stats=bb_stats)
+    sweep = None
+    if args.best_vs_best and args.gens == 0 and args.graph == 0:
+        log("H and BB at every compiled tile")
+        sweep = tile_sweep(m, op, step_fn, max(10, args.steps // 4), max(2, args.warmup // 4), stream)
 
     power = None
     if args.power > 0:
@@ -430,6 +484,8 @@ def main():
             "ms_per_step": bb_ms, "value": useful * gens / (bb_ms * 1e-3),
             "hbm_gbs_algorithmic": alg_bytes / (bb_ms * 1e-3) / 1e9},
         "h_vs_bb_speedup": None if bb_ms is None else bb_ms / h_ms,
+        "timing": {"h": h_stats or None, "bb": bb_stats or None},
+        "best_vs_best": None if not sweep else best_vs_best(sweep),
         "tiles": {"useful": info_h["useful_tiles"], "h_launched": info_h["launched_tiles"],
                   "bb_launched": info_bb["launched_tiles"], "wgs_per_tile": info_h["wgs_per_tile"],
                   "h_workgroups": info_h["launched_wgs"], "bb_workgroups": info_bb["launched_wgs"]},
@@ -440,7 +496,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
-            "kernel": f"{op} H launch" + (f" ({gens} generations per call, rho 128, halo 16)" if args.gens else ""),
+            "kernel": f"{op} H launch" + (f" ({gens} generations per call, "
+                                          + ("rho 128, halo 16)" if m == 2 else "rho 32, halo 4)")
+                                          if args.gens else ""),
             "kernel_sha": kernel_sha(op),
             "bytes_per_launch": alg_bytes,
             "copy_gbs": None if copy is None else copy["gbs"],

@@ -252,14 +252,16 @@ const char *simplex_strerror(int status);
 /* ---- several generations per launch -------------------------------------
  *
  * `steps` generations of the automaton (Section 5.1 runs a fixed number of
- * steps) with temporal blocking: each pass loads a tile plus a halo of 16
- * cells into LDS and advances it up to 16 generations there, so HBM is
+ * steps) with temporal blocking: each pass loads a tile plus a halo into
+ * LDS and advances it as many generations as the halo is wide, so HBM is
  * read and written once per pass instead of once per generation.
- * Supported: m = 2 with SMAP_OP_CA2 (others: SMAP_EUNSUPPORTED).
+ * Supported (others: SMAP_EUNSUPPORTED):
+ *   m = 2, SMAP_OP_CA2: 128 x 128 tiles, halo 16: up to G = 16 per pass;
+ *   m = 3, SMAP_OP_CA3: 32^3 tiles, halo 4: up to G = 4 per pass.
  *
  * buf_out receives the state after `steps` generations of buf_in (layout
  * and rules as for simplex_map_launch; the buffers must not overlap).
- * With steps <= 16 one pass runs and buf_in is left unchanged; with more,
+ * With steps <= G one pass runs and buf_in is left unchanged; with more,
  * passes alternate between the two buffers (an odd number of passes, the
  * last one writing buf_out) and buf_in's simplex cells are overwritten
  * with intermediate states.  Cells outside the simplex are never written.

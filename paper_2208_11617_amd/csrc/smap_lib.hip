@@ -19,6 +19,7 @@
 #include "smap_batch.hpp"
 #include "smap_ca2.hpp"
 #include "smap_ca2k.hpp"
+#include "smap_ca3k.hpp"
 #include "smap_ca3.hpp"
 #include "smap_plan.hpp"
 #include "smap_point.hpp"
@@ -944,11 +945,15 @@ int graph_create(int m, int64_t n, int r, int beta, int op, bool bb, const void 
 
 constexpr int kStepsRho = 128, kStepsKh = 16;   // tile side and halo (= generations per pass)
 constexpr TileCfg kStepsTile = {kStepsRho, 256, 1};
+// CA3: 32^3 tiles, 4-cell halo (4 generations per pass), 2 rows per thread
+constexpr int kSteps3Rho = 32, kSteps3Kh = 4, kSteps3Rl = 2;
+constexpr TileCfg kSteps3Tile = {kSteps3Rho, Ca3kShape<kSteps3Rho, kSteps3Kh, kSteps3Rl>::NT, 1};
 
 int steps_launch(int m, int64_t n, int r, int beta, int op, int32_t steps, void *a, void *b,
                  void *stream, bool bb)
 {
-    if (m != 2 || op != OP_CA2) return (check_op(m, n, op) != kOk) ? kEinval : kEunsupported;
+    const bool ca3 = m == 3 && op == OP_CA3;
+    if (!(m == 2 && op == OP_CA2) && !ca3) return (check_op(m, n, op) != kOk) ? kEinval : kEunsupported;
     if (steps < 1) return kEinval;
     int rc = check_op(m, n, op);
     if (rc != kOk) return rc;
@@ -962,12 +967,12 @@ int steps_launch(int m, int64_t n, int r, int beta, int op, int32_t steps, void 
     Plan P;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        rc = plan_for(m, n, bt, bb, 1, kStepsTile, &P, nullptr);
+        rc = plan_for(m, n, bt, bb, ca3 ? 2 : 1, ca3 ? kSteps3Tile : kStepsTile, &P, nullptr);
     }
     if (rc != kOk) return rc;
     if (P.total == 0) return kOk;
     const uint32_t kb = (uint32_t)P.kbox;
-    const dim3 grid = bb ? dim3(kb, kb, 1) : dim3(P.total, 1, 1);
+    const dim3 grid = bb ? dim3(kb, kb, ca3 ? kb : 1) : dim3(P.total, 1, 1);
     P.grid[0] = grid.x;
     P.grid[1] = grid.y;
     P.grid[2] = grid.z;
@@ -977,16 +982,21 @@ int steps_launch(int m, int64_t n, int r, int beta, int op, int32_t steps, void 
     P.remap = bb ? 0u : 1u;
     // passes of at most kStepsKh generations, alternating a -> b -> a ...;
     // an odd number of passes, so that the last one writes b
-    int passes = (steps + kStepsKh - 1) / kStepsKh;
+    const int kh = ca3 ? kSteps3Kh : kStepsKh;   // generations per pass at most
+    int passes = (steps + kh - 1) / kh;
     if (passes % 2 == 0) ++passes;
     hipStream_t s = (hipStream_t)stream;
     int left = steps;
     for (int i = 0; i < passes; ++i) {
-        const int g = (left + (passes - i) - 1) / (passes - i);   // spread evenly, 1..kStepsKh
+        const int g = (left + (passes - i) - 1) / (passes - i);   // spread evenly, 1..kh
         const uint8_t *src = (const uint8_t *)((i & 1) ? b : a);
         uint8_t *dst = (uint8_t *)((i & 1) ? a : b);
         const bool safe = n < 15;
-        if (bb) {
+        constexpr int nt3 = Ca3kShape<kSteps3Rho, kSteps3Kh, kSteps3Rl>::NT;
+        if (ca3) {
+            if (bb) hipLaunchKernelGGL((k_ca3k<kSteps3Rho, kSteps3Kh, kSteps3Rl, true>), grid, dim3(nt3), 0, s, P, src, dst, g);
+            else hipLaunchKernelGGL((k_ca3k<kSteps3Rho, kSteps3Kh, kSteps3Rl, false>), grid, dim3(nt3), 0, s, P, src, dst, g);
+        } else if (bb) {
             if (safe) hipLaunchKernelGGL((k_ca2k<kStepsRho, kStepsKh, true, true>), grid, dim3(256), 0, s, P, src, dst, g);
             else hipLaunchKernelGGL((k_ca2k<kStepsRho, kStepsKh, true, false>), grid, dim3(256), 0, s, P, src, dst, g);
         } else {

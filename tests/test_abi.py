@@ -207,7 +207,10 @@ def test_launch_steps_argument_errors():
     a, b = 4096, 1 << 24
     assert smap.launch_steps_raw(2, 100, "ca2", 0, a, b) == E          # steps < 1
     assert smap.launch_steps_raw(2, 100, "ca2", -3, a, b, use_bb=True) == E
-    assert smap.launch_steps_raw(3, 40, "ca3", 4, a, b) == U           # only the 2-D automaton
+    assert smap.launch_steps_raw(3, 40, "ca3", 0, a, b) == E          # steps < 1 (3-D)
+    assert smap.launch_steps_raw(4, 40, "hash", 4, a, b) == U          # automata only
+    assert smap.launch_steps_raw(3, 40, "ca2", 4, a, b) == E           # CA2 needs m = 2
+    assert smap.launch_steps_raw(3, 40, "ca3", 4, a, a + 100) == E     # overlapping buffers
     assert smap.launch_steps_raw(2, 100, "accum", 4, a, b) == U
     assert smap.launch_steps_raw(2, 100, "ca3", 4, a, b) == E          # CA3 needs m = 3
     assert smap.launch_steps_raw(2, 100, "ca2", 4, a, a + 100) == E     # overlapping buffers
