@@ -96,7 +96,7 @@ def tile_sweep(m, op, fn_for, steps, warmup, stream):
     rows = []
     smap.autotune_reset()   # H launches follow set_tile only without a tuned choice
     try:
-        for rho in (4, 8, 16, 32, 64, 128, 256, 512, 1024):
+        for rho in (4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096):
             for wg in (64, 128, 256, 512):
                 try:
                     smap.set_tile(m, op, rho, wg)

@@ -160,7 +160,9 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
  *                        m=4: rho 8 (256), 4 (64), 16 (256)
  *                        (the first listed rho of each m is the default)
  *   CA2 (m=2): rho 1024 (64 threads; 128 or 256), 512 (512), 256 (256),
- *              128 (128).
+ *              128 (128), 2048 (128 or 256), 4096 (256).  From 2048 on
+ *              the waves of a workgroup stand side by side along x, each
+ *              on a 1024-byte column of the tile.
  *   Large tiles are split into sub-blocks of rows (and planes), one
  *   workgroup each (wgs_per_tile in the plan info).
  *   CA3 (m=3): rho 128 (256 threads; 128 or 512), 256 (256), 64 (128 or

@@ -125,15 +125,20 @@ __device__ __forceinline__ uint32_t lane_next(const uint32_t *c, uint32_t e, int
     return sl == S - 1 ? e : d;
 }
 
-// Shape constants of a CA2 tile walk: S lanes per tile row, SEGS row
-// segments per wave, SUB sub-blocks (workgroups) per tile.
-template <int RHO, int W, int R>
+// Shape constants of a CA2 tile walk: the W waves of a workgroup stand WX
+// side by side along x (each on an RHO/WX-byte column) and W/WX deep along
+// y; S lanes per column row, SEGS row segments per wave, SUB sub-blocks
+// (workgroups) per tile.
+template <int RHO, int W, int R, int WX = 1>
 struct Ca2Walk {
-    static constexpr int S = RHO / 16;
+    static constexpr int SW = RHO / WX;          // bytes of a wave's column
+    static constexpr int S = SW / 16;
     static constexpr int SEGS = 64 / S;
-    static constexpr int SUB = RHO / (W * SEGS * R);
-    static_assert(S >= 2 && S <= 64 && 64 % S == 0 && R >= 1 && SUB >= 1 &&
-                  SUB * W * SEGS * R == RHO && (SUB & (SUB - 1)) == 0, "bad CA2 tile shape");
+    static constexpr int WY = W / WX;
+    static constexpr int SUB = RHO / (WY * SEGS * R);
+    static_assert(S >= 2 && S <= 64 && 64 % S == 0 && R >= 1 && SUB >= 1 && W % WX == 0 &&
+                  SW * WX == RHO && SUB * WY * SEGS * R == RHO && (SUB & (SUB - 1)) == 0,
+                  "bad CA2 tile shape");
 };
 
 // One Life step of sub-block `sub` of the rho x rho tile t (workgroup body).
@@ -141,20 +146,21 @@ struct Ca2Walk {
 // dwords); a segment of rho/16 lanes covers a tile row; each segment walks R
 // rows.  A tile is split into SUB = rho / (W * SEGS * R) sub-blocks of rows,
 // one workgroup each.
-template <int RHO, int W, int R, int D, bool SAFE>
+template <int RHO, int W, int R, int D, bool SAFE, int WX = 1>
 __device__ __forceinline__ void ca2_tile(const Plan &P, const uint8_t *__restrict__ in,
                                          uint8_t *__restrict__ out, const int32_t *t, uint32_t sub)
 {
-    constexpr int S = Ca2Walk<RHO, W, R>::S;
-    constexpr int SEGS = Ca2Walk<RHO, W, R>::SEGS;
+    using Sh = Ca2Walk<RHO, W, R, WX>;
+    constexpr int S = Sh::S, SEGS = Sh::SEGS, SW = Sh::SW, WY = Sh::WY;
     const int32_t n = P.n;
-    const int32_t x0 = t[0] * RHO, y0 = t[1] * RHO + (int32_t)sub * (W * SEGS * R);
-    if (x0 + y0 > n) return;
+    const int32_t xt = t[0] * RHO, y0 = t[1] * RHO + (int32_t)sub * (WY * SEGS * R);
+    if (xt + y0 > n) return;
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // scalar
     const int seg = lane / S, sl = lane % S;
-    const int32_t ywave = y0 + wave * SEGS * R;   // first row of the wave's first segment
+    const int32_t x0 = xt + (wave % WX) * SW;     // the wave's column
+    const int32_t ywave = y0 + (wave / WX) * SEGS * R;   // first row of the wave's first segment
     // rows after n - x0 hold no simplex cell in this tile column (wave-uniform)
     const int32_t rows = min(R, n - x0 - ywave + 1);
     if (rows <= 0) return;                          // whole wave idle (no barriers here)
@@ -162,7 +168,7 @@ __device__ __forceinline__ void ca2_tile(const Plan &P, const uint8_t *__restric
     const int64_t pitch = P.stride[1];
     const int64_t total = pitch * pitch;
     const int32_t x = x0 + 16 * sl;
-    const int32_t xe = (sl == 0) ? x0 - 4 : x0 + RHO;
+    const int32_t xe = (sl == 0) ? x0 - 4 : x0 + SW;
     const bool is_edge = (sl == 0) || (sl == S - 1);
     // Row r of the wave (r = -1 .. R) is addressed as a wave-uniform row
     // pointer (scalar) plus a per-lane 32-bit offset that is the same for
@@ -303,11 +309,11 @@ __device__ __forceinline__ void ca2_tile(const Plan &P, const uint8_t *__restric
 
 // The CA2 kernel: the launch grid is the map's grid times SUB (sub-blocks of
 // a tile adjacent in H, the y grid coordinate in BB).
-template <int RHO, int W, int R, int D, bool BB, bool SAFE>
+template <int RHO, int W, int R, int D, bool BB, bool SAFE, int WX = 1>
 __global__ __launch_bounds__(64 * W) void k_ca2(const Plan P, const uint8_t *__restrict__ in,
                                                 uint8_t *__restrict__ out)
 {
-    constexpr int SUB = Ca2Walk<RHO, W, R>::SUB;
+    constexpr int SUB = Ca2Walk<RHO, W, R, WX>::SUB;
     int32_t t[4] = {0, 0, 0, 0};
     uint32_t sub;
     const WgId g = wg_id(P);
@@ -318,7 +324,7 @@ __global__ __launch_bounds__(64 * W) void k_ca2(const Plan P, const uint8_t *__r
         if (!decode_h<2>(P, g.x / SUB, t)) return;
         sub = g.x % SUB;
     }
-    ca2_tile<RHO, W, R, D, SAFE>(P, in, out, t, sub);
+    ca2_tile<RHO, W, R, D, SAFE, WX>(P, in, out, t, sub);
 }
 
 }  // namespace smap

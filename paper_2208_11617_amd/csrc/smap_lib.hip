@@ -42,6 +42,8 @@ struct Ca2Shape {
 constexpr Ca2Shape kCa2Shapes[] = {
     {1024, 64, 1, 16, 64}, {1024, 128, 2, 16, 32}, {1024, 256, 4, 16, 16},
     {512, 512, 8, 16, 2},  {256, 256, 4, 16, 1},   {128, 128, 2, 8, 1},
+    // waves side by side along x: 1 KB columns, 2 or 4 per workgroup
+    {2048, 128, 2, 16, 128}, {2048, 256, 4, 16, 64}, {4096, 256, 4, 16, 256},
 };
 
 // Pointwise shapes: (m, rho) -> threads, sub-blocks per tile.
@@ -343,19 +345,23 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
 #endif
         constexpr int D = SMAP_CA2_D;  // rows per block; two blocks in flight per wave
         switch (tc.rho * 10000 + tc.wg) {
-#define SMAP_CA2(RHO, WG, W, R)                                                                  \
+#define SMAP_CA2(RHO, WG, W, R, WX)                                                              \
         case RHO * 10000 + WG:                                                                    \
+            static_assert(Ca2Walk<RHO, W, R, WX>::SUB > 0, "shape");                              \
             if (P.n < 15)                                                                         \
-                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, true>), grid, dim3(WG), 0, s, PL, i8, o8); \
+                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, true, WX>), grid, dim3(WG), 0, s, PL, i8, o8); \
             else                                                                                  \
-                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, false>), grid, dim3(WG), 0, s, PL, i8, o8); \
+                hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, false, WX>), grid, dim3(WG), 0, s, PL, i8, o8); \
             return kOk;
-        SMAP_CA2(1024, 64, 1, 16)
-        SMAP_CA2(1024, 128, 2, 16)
-        SMAP_CA2(1024, 256, 4, 16)
-        SMAP_CA2(512, 512, 8, 16)
-        SMAP_CA2(256, 256, 4, 16)
-        SMAP_CA2(128, 128, 2, 8)
+        SMAP_CA2(1024, 64, 1, 16, 1)
+        SMAP_CA2(1024, 128, 2, 16, 1)
+        SMAP_CA2(1024, 256, 4, 16, 1)
+        SMAP_CA2(512, 512, 8, 16, 1)
+        SMAP_CA2(256, 256, 4, 16, 1)
+        SMAP_CA2(128, 128, 2, 8, 1)
+        SMAP_CA2(2048, 128, 2, 16, 2)
+        SMAP_CA2(2048, 256, 4, 16, 2)
+        SMAP_CA2(4096, 256, 4, 16, 4)
 #undef SMAP_CA2
         }
         return kEunsupported;

@@ -20,7 +20,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 POINT_TILES = {2: [16, 32, 64, 128], 3: [8, 16, 32], 4: [4, 8, 16]}
-CA2_TILES = [(1024, 64), (1024, 128), (1024, 256), (512, 512), (256, 256), (128, 128)]
+CA2_TILES = [(1024, 64), (1024, 128), (1024, 256), (512, 512), (256, 256), (128, 128),
+             (2048, 128), (2048, 256), (4096, 256)]
 
 
 def say(*a):
@@ -142,7 +143,7 @@ def test_map_writes_nothing(smap):
 # --------------------------------------------------------------- automata
 
 CA2_SIZES = list(range(0, 70)) + [127, 128, 129, 255, 256, 257, 300, 511, 512, 513,
-                                  767, 1000, 1023, 1024, 1025, 2047, 2049]
+                                  767, 1000, 1023, 1024, 1025, 2047, 2049, 4095, 4097, 8200]
 
 
 def test_ca2_parity(smap):

@@ -24,7 +24,7 @@ TILES = {  # (m, op) -> supported rho values
     (2, "hits"): [16, 32, 64, 128],
     (3, "hits"): [8, 16, 32],
     (4, "hits"): [4, 8, 16],
-    (2, "ca2"): [128, 256, 512, 1024],
+    (2, "ca2"): [128, 256, 512, 1024, 2048, 4096],
     (3, "ca3"): [32, 64, 128, 256],
 }
 
