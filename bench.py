@@ -301,7 +301,22 @@ def cpu_baseline(w, budget_s=12.0):
         "kind": "oracle",
         "sample": f"{done_cells} of {oracle.count(m, n)} elements (slabs x_{m} < {lo}), "
                   f"{elapsed:.1f} s single-threaded",
+        "host_cpu": host_cpu(),
     }
+
+
+def host_cpu():
+    """The host's CPU model and the logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus_available": len(os.sched_getaffinity(0))}
 
 
 def main():
