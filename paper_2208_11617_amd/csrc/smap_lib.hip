@@ -315,11 +315,7 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
         else
             grid = (m == 2) ? dim3(kb, kb, sub) : (m == 3 ? dim3(kb, kb, kb * sub) : dim3(kb, kb, kb * kb * sub));
     } else {
-#ifdef SMAP_CA3_TILE_MAJOR
-        grid = dim3(P.total * sub, 1, 1);
-#else
         grid = (op == OP_CA3) ? dim3(P.total, sub, 1) : dim3(P.total * sub, 1, 1);
-#endif
     }
     Plan PL = P0;  // the kernels renumber workgroups over this grid
     PL.grid[0] = grid.x;
