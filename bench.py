@@ -512,7 +512,7 @@ def main():
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
             "kernel": f"{op} H launch" + (f" ({gens} generations per call, "
-                                          + ("rho 128, halo 16)" if m == 2 else "rho 32, halo 4)")
+                                          + ("rho 128, halo 16)" if m == 2 else "rho 64, halo 16)")
                                           if args.gens else ""),
             "kernel_sha": kernel_sha(op),
             "bytes_per_launch": alg_bytes,

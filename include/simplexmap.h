@@ -259,7 +259,7 @@ const char *simplex_strerror(int status);
  * read and written once per pass instead of once per generation.
  * Supported (others: SMAP_EUNSUPPORTED):
  *   m = 2, SMAP_OP_CA2: 128 x 128 tiles, halo 16: up to G = 16 per pass;
- *   m = 3, SMAP_OP_CA3: 32^3 tiles, halo 4: up to G = 4 per pass.
+ *   m = 3, SMAP_OP_CA3: 64^3 tiles, halo 16: up to G = 16 per pass.
  *
  * buf_out receives the state after `steps` generations of buf_in (layout
  * and rules as for simplex_map_launch; the buffers must not overlap).

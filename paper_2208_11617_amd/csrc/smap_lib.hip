@@ -947,9 +947,9 @@ int graph_create(int m, int64_t n, int r, int beta, int op, bool bb, const void 
 
 constexpr int kStepsRho = 128, kStepsKh = 16;   // tile side and halo (= generations per pass)
 constexpr TileCfg kStepsTile = {kStepsRho, Ca2kShape<kStepsRho, kStepsKh>::NT, 1};
-// CA3: 32^3 tiles, 4-cell halo (4 generations per pass), 2 rows per thread
-constexpr int kSteps3Rho = 32, kSteps3Kh = 4, kSteps3Rl = 2;
-constexpr TileCfg kSteps3Tile = {kSteps3Rho, Ca3kShape<kSteps3Rho, kSteps3Kh, kSteps3Rl>::NT, 1};
+// CA3: 64^3 tiles, 16-cell halo (16 generations per pass), one bit per cell
+constexpr int kSteps3Rho = 64, kSteps3Kh = 16;
+constexpr TileCfg kSteps3Tile = {kSteps3Rho, Ca3kShape<kSteps3Rho, kSteps3Kh>::NT, 1};
 
 int steps_launch(int m, int64_t n, int r, int beta, int op, int32_t steps, void *a, void *b,
                  void *stream, bool bb)
@@ -994,11 +994,16 @@ int steps_launch(int m, int64_t n, int r, int beta, int op, int32_t steps, void 
         const uint8_t *src = (const uint8_t *)((i & 1) ? b : a);
         uint8_t *dst = (uint8_t *)((i & 1) ? a : b);
         const bool safe = n < 15;
-        constexpr int nt3 = Ca3kShape<kSteps3Rho, kSteps3Kh, kSteps3Rl>::NT;
+        constexpr int nt3 = Ca3kShape<kSteps3Rho, kSteps3Kh>::NT;
         constexpr int nt2 = Ca2kShape<kStepsRho, kStepsKh>::NT;
         if (ca3) {
-            if (bb) hipLaunchKernelGGL((k_ca3k<kSteps3Rho, kSteps3Kh, kSteps3Rl, true>), grid, dim3(nt3), 0, s, P, src, dst, g);
-            else hipLaunchKernelGGL((k_ca3k<kSteps3Rho, kSteps3Kh, kSteps3Rl, false>), grid, dim3(nt3), 0, s, P, src, dst, g);
+            if (bb) {
+                if (safe) hipLaunchKernelGGL((k_ca3k<kSteps3Rho, kSteps3Kh, true, true>), grid, dim3(nt3), 0, s, P, src, dst, g);
+                else hipLaunchKernelGGL((k_ca3k<kSteps3Rho, kSteps3Kh, true, false>), grid, dim3(nt3), 0, s, P, src, dst, g);
+            } else {
+                if (safe) hipLaunchKernelGGL((k_ca3k<kSteps3Rho, kSteps3Kh, false, true>), grid, dim3(nt3), 0, s, P, src, dst, g);
+                else hipLaunchKernelGGL((k_ca3k<kSteps3Rho, kSteps3Kh, false, false>), grid, dim3(nt3), 0, s, P, src, dst, g);
+            }
         } else if (bb) {
             if (safe) hipLaunchKernelGGL((k_ca2k<kStepsRho, kStepsKh, true, true>), grid, dim3(nt2), 0, s, P, src, dst, g);
             else hipLaunchKernelGGL((k_ca2k<kStepsRho, kStepsKh, true, false>), grid, dim3(nt2), 0, s, P, src, dst, g);
