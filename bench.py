@@ -283,17 +283,24 @@ def cpu_baseline(w, budget_s=12.0):
     slab_cells = (n + 1) ** (m - 1)
     done_cells, elapsed, lo = 0, 0.0, 0
     step = max(1, (n + 1) // 64)
-    while lo <= n and elapsed < budget_s:
-        hi = min(lo + step, n + 1)
-        if inp is not None:  # this slab and the next one (read by the automaton)
-            for z in range(lo, min(hi + 1, n + 1)):
-                flat = si.values_at(w["seed"], w["dist"], w["p"],
-                                    np.arange(z * slab_cells, (z + 1) * slab_cells))
-                inp[z] = flat.reshape((n + 1,) * (m - 1))
-        t0 = time.perf_counter()
-        done_cells += oracle.apply_slab(m, n, op, inp, out, lo, hi)
-        elapsed += time.perf_counter() - t0
-        lo = hi
+    # the oracle runs on one core: pin the process to one allowed CPU meanwhile
+    allowed = os.sched_getaffinity(0)
+    pinned = min(allowed)
+    os.sched_setaffinity(0, {pinned})
+    try:
+        while lo <= n and elapsed < budget_s:
+            hi = min(lo + step, n + 1)
+            if inp is not None:  # this slab and the next one (read by the automaton)
+                for z in range(lo, min(hi + 1, n + 1)):
+                    flat = si.values_at(w["seed"], w["dist"], w["p"],
+                                        np.arange(z * slab_cells, (z + 1) * slab_cells))
+                    inp[z] = flat.reshape((n + 1,) * (m - 1))
+            t0 = time.perf_counter()
+            done_cells += oracle.apply_slab(m, n, op, inp, out, lo, hi)
+            elapsed += time.perf_counter() - t0
+            lo = hi
+    finally:
+        os.sched_setaffinity(0, allowed)
     return {
         "value": done_cells / elapsed if elapsed > 0 else None,
         "unit": "useful elements/s",
@@ -302,6 +309,7 @@ def cpu_baseline(w, budget_s=12.0):
         "sample": f"{done_cells} of {oracle.count(m, n)} elements (slabs x_{m} < {lo}), "
                   f"{elapsed:.1f} s single-threaded",
         "host_cpu": host_cpu(),
+        "pinned_cpu": pinned,
     }
 
 
