@@ -520,7 +520,7 @@ def main():
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
             "kernel": f"{op} H launch" + (f" ({gens} generations per call, "
-                                          + ("rho 128, halo 16)" if m == 2 else "rho 64, halo 16)")
+                                          + ("rho 256, halo 32)" if m == 2 else "rho 64, halo 16)")
                                           if args.gens else ""),
             "kernel_sha": kernel_sha(op),
             "bytes_per_launch": alg_bytes,

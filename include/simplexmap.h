@@ -258,7 +258,7 @@ const char *simplex_strerror(int status);
  * LDS and advances it as many generations as the halo is wide, so HBM is
  * read and written once per pass instead of once per generation.
  * Supported (others: SMAP_EUNSUPPORTED):
- *   m = 2, SMAP_OP_CA2: 128 x 128 tiles, halo 16: up to G = 16 per pass;
+ *   m = 2, SMAP_OP_CA2: 256 x 256 tiles, halo 32: up to G = 32 per pass;
  *   m = 3, SMAP_OP_CA3: 64^3 tiles, halo 16: up to G = 16 per pass.
  *
  * buf_out receives the state after `steps` generations of buf_in (layout

@@ -34,7 +34,7 @@ template <int RHO, int KH>
 struct Ca2kShape {
     static constexpr int W = RHO + 2 * KH;   // cells per staged row (and rows)
     static constexpr int DW = W / 32;         // dwords (32 cells) per staged row
-    static constexpr int NT = 64;             // threads: one wave
+    static constexpr int NT = W <= 160 ? 64 : 256;   // threads
     static constexpr int SEGS = NT / DW;      // row runs per dword column
     static constexpr int RUN = (W + SEGS - 1) / SEGS;
     static_assert(KH % 16 == 0 && RHO % 32 == 0 && W % 32 == 0 && DW <= NT, "bad CA2K shape");
@@ -48,14 +48,14 @@ __device__ __forceinline__ uint32_t ca2k_keep_mask(int32_t x, int32_t y, int32_t
     return keep >= 4 ? 0xFFFFFFFFu : (keep <= 0 ? 0u : (1u << (8 * keep)) - 1u);
 }
 
-// Simplex cells of the 32 cells x .. x+31 of row y, as bits (x >= -16:
-// only a whole low half can lie left of the box).
+// Simplex cells of the 32 cells x .. x+31 of row y, as bits (cells left of
+// the box, x < 0, and past the hypotenuse cleared).
 __device__ __forceinline__ uint32_t ca2k_keep_bits(int32_t x, int32_t y, int32_t n)
 {
-    if (y < 0) return 0u;
+    if (y < 0 || x <= -32) return 0u;
     const int32_t hi = n - y - x + 1;               // cells x .. x+hi-1 satisfy x + y <= n
     uint32_t m = hi >= 32 ? 0xFFFFFFFFu : (hi <= 0 ? 0u : (1u << hi) - 1u);
-    if (x < 0) m &= 0xFFFF0000u;                    // x = -16: the low half is left of the box
+    if (x < 0) m &= 0xFFFFFFFFu << (-x);            // the low -x cells are left of the box
     return m;
 }
 
@@ -188,11 +188,12 @@ __device__ __forceinline__ void ca2k_tile(const Plan &P, const uint8_t *__restri
     }
 }
 
+// (the launch bound is Ca2kShape<RHO, KH>::NT, written without commas)
 template <int RHO, int KH, bool BB, bool SAFE>
-__global__ __launch_bounds__(64) void k_ca2k(const Plan P, const uint8_t *__restrict__ in,
-                                             uint8_t *__restrict__ out, int gens)
+__global__ __launch_bounds__(RHO + 2 * KH <= 160 ? 64 : 256) void k_ca2k(const Plan P, const uint8_t *__restrict__ in,
+                                                                        uint8_t *__restrict__ out, int gens)
 {
-    static_assert(Ca2kShape<RHO, KH>::NT == 64, "launch bound");
+    static_assert(Ca2kShape<RHO, KH>::NT == (RHO + 2 * KH <= 160 ? 64 : 256), "launch bound");
     int32_t t[4] = {0, 0, 0, 0};
     const WgId g = wg_id(P);
     if (BB) {

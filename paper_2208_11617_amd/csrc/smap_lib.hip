@@ -945,7 +945,7 @@ int graph_create(int m, int64_t n, int r, int beta, int op, bool bb, const void 
 
 // ---- several generations per pass (CA2) ------------------------------------
 
-constexpr int kStepsRho = 128, kStepsKh = 16;   // tile side and halo (= generations per pass)
+constexpr int kStepsRho = 256, kStepsKh = 32;   // tile side and halo (= generations per pass)
 constexpr TileCfg kStepsTile = {kStepsRho, Ca2kShape<kStepsRho, kStepsKh>::NT, 1};
 // CA3: 64^3 tiles, 16-cell halo (16 generations per pass), one bit per cell
 constexpr int kSteps3Rho = 64, kSteps3Kh = 16;

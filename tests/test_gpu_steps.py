@@ -58,7 +58,7 @@ def test_steps_match_oracle(smap, kind):
             assert np.array_equal(got, want), (kind, n, steps)
             after_in = d_in.cpu().numpy()
             assert np.array_equal(after_in[~inside], inp[~inside])      # outside never written
-            if steps <= 16:
+            if steps <= 32:
                 assert np.array_equal(after_in, inp)                   # one pass: input untouched
 
 
