@@ -468,10 +468,14 @@ def main():
         h_rate, h_w, h_n = power_leg(step_fn(h_launch), args.power, stream)
         power = {"idle_w": idle, "h": {"launches_per_s": h_rate, "watts": h_w, "samples": h_n,
                                        "elements_per_joule": None if not h_w else useful * gens * h_rate / h_w}}
-        if not args.no_bb and args.gens == 0 and args.graph == 0:
-            b_rate, b_w, b_n = power_leg(step_fn(smap.bb_launch), args.power, stream)
+        if not args.no_bb and args.graph == 0:
+            bb_fn = smap.bb_launch
+            if args.gens > 0:
+                bb_fn = lambda m_, n_, op_, s_, d_, stream=None: smap.bb_launch_steps(  # noqa: E731
+                    m_, n_, op_, gens, s_, d_, stream=stream)
+            b_rate, b_w, b_n = power_leg(step_fn(bb_fn), args.power, stream)
             power["bb"] = {"launches_per_s": b_rate, "watts": b_w, "samples": b_n,
-                           "elements_per_joule": None if not b_w else useful * b_rate / b_w}
+                           "elements_per_joule": None if not b_w else useful * gens * b_rate / b_w}
 
     copy = None
     if not args.no_copy:
