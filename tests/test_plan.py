@@ -226,3 +226,32 @@ def test_levels_layout_3d_covers_exactly_once_without_waste():
         smap.set_layout(2, smap.LAYOUT_LEVELS)
     with pytest.raises(smap.SimplexMapError):
         smap.set_layout(3, 7)
+
+
+def test_concurrent_plan_queries_match_sequential():
+    """The plan cache is shared and mutex-guarded: plan queries from several
+    threads at once (ctypes releases the interpreter lock during the call)
+    give the same answers as the same queries made one by one."""
+    import threading
+    keys = [(m, n, op, beta) for m, op, beta in ((2, "ca2", 0), (3, "ca3", 0), (4, "hash", 3), (4, "hash", 4),
+                                                 (2, "accum", 0), (3, "hits", 0))
+            for n in (7, 63, 129, 300, 1023) if m < 4 or n <= 300]
+    want = {k: smap.plan_info(k[0], k[1], k[2], beta=k[3]) for k in keys}
+    got, errors = {}, []
+
+    def worker(part):
+        try:
+            for _ in range(20):
+                for k in part:
+                    got[k] = smap.plan_info(k[0], k[1], k[2], beta=k[3])
+                    assert got[k] == want[k], k
+        except Exception as e:   # collected and re-raised in the main thread
+            errors.append(e)
+    threads = [threading.Thread(target=worker, args=(keys[i::4] + keys[:3],)) for i in range(4)]
+    smap.lib().simplex_autotune_reset()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors[0]
+    assert got == want
