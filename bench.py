@@ -349,6 +349,8 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotune result file (read and appended)")
     ap.add_argument("--graph", type=int, default=0,
                     help="time H as replays of a captured graph of this many launches")
+    ap.add_argument("--general", default="fused", choices=["fused", "streams"],
+                    help="H launches: all pieces in one launch, or one launch per piece on streams of their own")
     ap.add_argument("--layout3", default="packed", choices=["packed", "levels"],
                     help="native layout of the 3-D H map")
     ap.add_argument("--gens", type=int, default=0,
@@ -387,6 +389,7 @@ def main():
     useful = smap.count(m, n)
     if m == 3:
         smap.set_layout(3, smap.LAYOUT_LEVELS if args.layout3 == "levels" else smap.LAYOUT_PACKED)
+    smap.set_general(smap.GENERAL_STREAMS if args.general == "streams" else smap.GENERAL_FUSED)
 
     log(f"generating {args.workload}: m={m} n={n} op={op}")
     bufs = []
@@ -505,7 +508,8 @@ def main():
         "config": {"workload": f"{args.workload}: m={m} n={n} op={op}", "m": m, "n": n,
                    "op": op, "useful_elements": useful, "rho": info_h["rho"],
                    "beta": info_h["beta"], "autotuned": tuned, "graph_launches": args.graph or None,
-                   "generations_per_call": gens, "layout3": args.layout3 if m == 3 else None},
+                   "generations_per_call": gens, "layout3": args.layout3 if m == 3 else None,
+                   "general": args.general},
         "hbm_gbs_algorithmic": achieved,
         "bb": None if bb_ms is None else {
             "ms_per_step": bb_ms, "value": useful * gens / (bb_ms * 1e-3),

@@ -189,6 +189,25 @@ int simplex_set_tile(int m, int op, int rho, int wg_threads);
 #define SMAP_LAYOUT_LEVELS 1
 int simplex_set_layout(int m, int layout);
 
+/*
+ * How an H launch (simplex_map_launch) runs the pieces of its plan when n is
+ * not of the native form (the native map plus the shell pieces, which play
+ * the role of the concurrent trapezoids of Section 4.2), in later calls of
+ * this process:
+ *   SMAP_GENERAL_FUSED (default): all pieces in one launch; a workgroup
+ *     finds its piece from the piece table.
+ *   SMAP_GENERAL_STREAMS: one launch per piece, each on a stream of its own
+ *     so the pieces run concurrently.  The streams (default priority) and
+ *     their events are created on the first such launch on a device and kept
+ *     until the process ends; the pieces start after the work already
+ *     enqueued on the caller's stream, and later work on that stream waits
+ *     for all of them.  Results are identical to the fused launch.
+ * Errors: SMAP_EINVAL for an unknown strategy.
+ */
+#define SMAP_GENERAL_FUSED 0
+#define SMAP_GENERAL_STREAMS 1
+int simplex_set_general(int strategy);
+
 /* ---- autotuning and graphs ------------------------------------------------
  *
  * Theorem 3 (Section 6) frames the choice of the scale and replication

@@ -24,9 +24,11 @@ EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_strerror", "simplex_batch_launch", "simplex_serve_run",
            "simplex_autotune", "simplex_autotune_reset", "simplex_graph_create",
            "simplex_graph_launch", "simplex_graph_destroy", "simplex_map_launch_steps",
-           "simplex_bb_launch_steps", "simplex_set_layout", "simplex_queue_launch")
+           "simplex_bb_launch_steps", "simplex_set_layout", "simplex_queue_launch",
+           "simplex_set_general")
 
 LAYOUT_PACKED, LAYOUT_LEVELS = 0, 1
+GENERAL_FUSED, GENERAL_STREAMS = 0, 1
 
 SERVE_SEQUENTIAL, SERVE_BATCHED, SERVE_PERSISTENT = 0, 1, 2
 
@@ -117,6 +119,8 @@ def lib():
     L.simplex_set_tile.restype = ci
     L.simplex_batch_launch.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, vp]
     L.simplex_batch_launch.restype = ci
+    L.simplex_set_general.argtypes = [ci]
+    L.simplex_set_general.restype = ci
     L.simplex_queue_launch.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_int32, vp]
     L.simplex_queue_launch.restype = ci
     L.simplex_serve_run.argtypes = [ctypes.POINTER(ServeJob), ctypes.c_int32, vp, u64, ctypes.c_int32,
@@ -341,6 +345,12 @@ def launch_steps_raw(m, n, op, steps, in_ptr, out_ptr, use_bb=False) -> int:
     if use_bb:
         return L.simplex_bb_launch_steps(m, n, _op(op), steps, in_ptr, out_ptr, None)
     return L.simplex_map_launch_steps(m, n, 0, 0, _op(op), steps, in_ptr, out_ptr, None)
+
+
+def set_general(strategy) -> None:
+    """How H launches run their plan's pieces: GENERAL_FUSED (default, one
+    launch) or GENERAL_STREAMS (one launch per piece, on streams of their own)."""
+    _check(lib().simplex_set_general(strategy), "simplex_set_general")
 
 
 def set_layout(m, layout) -> None:

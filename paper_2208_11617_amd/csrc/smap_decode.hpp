@@ -117,6 +117,8 @@ struct Plan {
     uint32_t nwg;                // grid[0] * grid[1] * grid[2] (< 2^32)
     uint32_t remap;              // 1: renumber workgroups with xcd_remap
     int32_t layout3;             // m = 3 native part: 0 packed grid, 1 one range per level
+    uint32_t wg_base;            // first map index of this launch (0; a piece's start when
+                                 // the pieces run as launches of their own)
 };
 
 // Launch order.  The 8 XCDs of the chip each have their own L2; workgroup L
@@ -317,6 +319,7 @@ template <int M>
 SMAP_HD bool decode_h(const Plan &P, uint32_t w, int32_t *t)
 {
     constexpr int m = M;
+    w += P.wg_base;
     // piece: last p with piece_start[p] <= w (unrolled: no runtime-indexed reads)
     // (scalar fields selected one by one: a selected struct or array element
     // would be turned into a runtime-indexed local copy in scratch memory)

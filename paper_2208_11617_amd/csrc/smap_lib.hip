@@ -130,6 +130,7 @@ struct CachedPlan {
 };
 std::map<std::tuple<int, int64_t, int, int, int, int, int>, CachedPlan> g_plans;  // (m,n,beta,rho,bb,cls,layout)
 int g_layout3 = 0;  // H native layout for m = 3 (simplex_set_layout)
+int g_general = 0;  // H launch of the pieces: 0 fused, 1 one launch per piece (simplex_set_general)
 
 TileCfg tile_for(int m, int cls)
 {
@@ -387,6 +388,57 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
     return dispatch_point<BB>(op, m, tc.rho, PL, grid, in, out, s);
 }
 
+// The pieces of an H launch as concurrent launches: one stream per piece
+// (created once per device, default priority), joined to the caller's
+// stream through events.  g_piece_mu keeps one launch's record/wait
+// sequence together.
+struct PieceStreams {
+    hipStream_t s[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t start = nullptr;
+    hipEvent_t done[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+std::mutex g_piece_mu;
+std::map<int, PieceStreams> g_piece_streams;
+
+int piece_streams_for_device(PieceStreams **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kEhip;
+    PieceStreams &S = g_piece_streams[dev];
+    if (!S.start) {
+        for (int i = 0; i < 4; ++i) {
+            if (hipStreamCreateWithFlags(&S.s[i], hipStreamNonBlocking) != hipSuccess) return kEhip;
+            if (hipEventCreateWithFlags(&S.done[i], hipEventDisableTiming) != hipSuccess) return kEhip;
+        }
+        if (hipEventCreateWithFlags(&S.start, hipEventDisableTiming) != hipSuccess) return kEhip;
+    }
+    *out = &S;
+    return kOk;
+}
+
+int launch_pieces(int m, int op, const TileCfg &tc, const Plan &P, const void *in, void *out, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_piece_mu);
+    PieceStreams *S = nullptr;
+    int rc = piece_streams_for_device(&S);
+    if (rc != kOk) return rc;
+    if (hipEventRecord(S->start, s) != hipSuccess) return kEhip;
+    for (int p = 0; p < P.npieces; ++p) {
+        Plan Q = P;
+        Q.wg_base = P.piece_start[p];
+        Q.total = P.piece_start[p + 1] - P.piece_start[p];
+        if (hipStreamWaitEvent(S->s[p], S->start, 0) != hipSuccess) return kEhip;
+        if (Q.total > 0) {
+            rc = dispatch<false>(m, op, tc, Q, in, out, S->s[p]);
+            if (rc != kOk) return rc;
+        }
+        if (hipEventRecord(S->done[p], S->s[p]) != hipSuccess) return kEhip;
+    }
+    for (int p = 0; p < P.npieces; ++p)
+        if (hipStreamWaitEvent(s, S->done[p], 0) != hipSuccess) return kEhip;
+    return kOk;
+}
+
 int do_launch(int m, int64_t n, int r, int beta, int op, const void *in, void *out,
               void *stream, bool bb)
 {
@@ -410,7 +462,15 @@ int do_launch(int m, int64_t n, int r, int beta, int op, const void *in, void *o
     if (rc != kOk) return rc;
     if (P.total == 0) return kOk;
     hipStream_t s = (hipStream_t)stream;
-    rc = bb ? dispatch<true>(m, op, tc, P, in, out, s) : dispatch<false>(m, op, tc, P, in, out, s);
+    int general = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        general = g_general;
+    }
+    if (!bb && general == 1 && P.npieces > 1)
+        rc = launch_pieces(m, op, tc, P, in, out, s);
+    else
+        rc = bb ? dispatch<true>(m, op, tc, P, in, out, s) : dispatch<false>(m, op, tc, P, in, out, s);
     if (rc != kOk) return rc;
     return hipGetLastError() == hipSuccess ? kOk : kEhip;
 }
@@ -1228,6 +1288,14 @@ int simplex_bb_launch_steps(int m, int64_t n, int op, int32_t steps, void *buf_i
                             void *stream)
 {
     return steps_launch(m, n, 0, 0, op, steps, buf_in, buf_out, stream, true);
+}
+
+int simplex_set_general(int strategy)
+{
+    if (strategy != SMAP_GENERAL_FUSED && strategy != SMAP_GENERAL_STREAMS) return kEinval;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_general = strategy;
+    return kOk;
 }
 
 int simplex_set_layout(int m, int layout)

@@ -146,6 +146,12 @@ def test_batch_launch_argument_errors():
     assert smap.batch_launch_raw([good, (2, "ca2", 100, 4096, 4096 + 50)]) == E  # overlap
 
 
+def test_set_general_argument_errors():
+    assert smap.lib().simplex_set_general(2) == smap.EINVAL
+    assert smap.lib().simplex_set_general(-1) == smap.EINVAL
+    assert smap.lib().simplex_set_general(smap.GENERAL_FUSED) == smap.OK
+
+
 def test_queue_launch_argument_errors():
     """simplex_queue_launch validates every job and the workgroup cap first."""
     E = smap.EINVAL

@@ -371,3 +371,58 @@ def test_levels_layout_3d(smap):
         smap.set_tile(3, "hits", 0)
         smap.set_tile(3, "ca3", 0)
         smap.set_layout(3, smap.LAYOUT_PACKED)
+
+
+# ---- the pieces as concurrent launches (Section 4.2's concurrent trapezoids)
+
+def test_pieces_on_streams(smap):
+    """SMAP_GENERAL_STREAMS: the native part and each shell piece run as
+    launches of their own on separate streams.  Exactly-once coverage (HITS)
+    over the n sweep for every m, every op bit-exact against the oracle, and
+    the full-size workloads equal to the fused launch."""
+    smap.set_general(smap.GENERAL_STREAMS)
+    try:
+        for m in (2, 3, 4):
+            for n in _sweep(m):
+                want = to_dev(expected(m, n, "hits", None))
+                for beta in ((3, 4) if m == 4 else (0,)):
+                    say(f"streams hits m={m} n={n} beta={beta}")
+                    d = fresh_out(m, n, "hits")
+                    launch(smap, "h", m, n, "hits", None, d, beta)
+                    assert same(d, want), (m, n, beta)
+        for m, op, sizes in ((2, "ca2", [0, 1, 14, 15, 16, 100, 1000, 1025, 2049]),
+                             (3, "ca3", [0, 14, 15, 16, 40, 65, 130]),
+                             (2, "accum", [0, 1, 40, 300]), (4, "hash", [0, 5, 33]),
+                             (2, "edm", [0, 1, 31, 33, 300])):
+            for n in sizes:
+                say(f"streams {op} m={m} n={n}")
+                if op == "edm":
+                    pts = si.points(n, 3600 + n)
+                    d_out = fresh_out(m, n, "accum")
+                    smap.map_launch(m, n, "edm", torch.from_numpy(pts).cuda(), d_out)
+                    torch.cuda.synchronize()
+                    _edm_check(to_host(d_out, np.uint32).reshape(n + 1, n + 1), oracle.edm(n, pts), n)
+                    continue
+                dist = {"ca2": "bern", "ca3": "bern", "accum": "u31"}.get(op)
+                inp = si.box(m, n, dist, 3600 + n, p=0.3) if dist else None
+                want = to_dev(expected(m, n, op, inp))
+                d_out = fresh_out(m, n, op)
+                launch(smap, "h", m, n, op, None if inp is None else to_dev(inp), d_out)
+                assert same(d_out, want), (op, n)
+        for name in ("c2", "c3", "c4"):
+            w = si.WORKLOADS[name]
+            m, n, op = w["m"], w["n"], w["op"]
+            u8 = op.startswith("ca")
+            d_in = si.box_torch(m, n, w["dist"], w["seed"], p=w["p"], device="cuda") if w["dist"] else None
+            outs = []
+            for strategy in (smap.GENERAL_STREAMS, smap.GENERAL_FUSED):
+                smap.set_general(strategy)
+                say(f"streams workload {name} strategy={strategy}")
+                d_out = si.sentinel_box_torch(m, n, u8)
+                launch(smap, "h", m, n, op, d_in, d_out)
+                outs.append(d_out)
+            assert torch.equal(outs[0], outs[1]), name
+            del outs, d_in
+            smap.set_general(smap.GENERAL_STREAMS)
+    finally:
+        smap.set_general(smap.GENERAL_FUSED)
