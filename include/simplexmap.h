@@ -368,6 +368,25 @@ int simplex_batch_launch(const struct simplex_job *jobs, int32_t njobs, void *st
 int simplex_queue_launch(const struct simplex_job *jobs, int32_t njobs, int32_t max_workgroups,
                          void *stream);
 
+/*
+ * Captures ONE persistent work-queue launch (simplex_queue_launch) over the
+ * fixed job set jobs[0..njobs) into a graph, for replay with
+ * simplex_graph_launch and release with simplex_graph_destroy.  The job
+ * table (head counter, unit prefix sums, jobs' plans and pointers) is
+ * copied once, at creation, into device memory that the graph owns (freed
+ * by simplex_graph_destroy); each replay first clears the head counter with
+ * a one-workgroup fill kernel (the graph holds no memset node), then runs
+ * the queue kernel.  The jobs' buffers must stay valid while the graph
+ * exists; a replay reads buf_in and writes buf_out of every job, so
+ * replays that overlap on the device race on those buffers (and on the
+ * head counter).  njobs is at most 4096 (SMAP_ERANGE beyond);
+ * max_workgroups as for simplex_queue_launch.  Errors: those of
+ * simplex_queue_launch, SMAP_EINVAL for a NULL graph or njobs < 1,
+ * SMAP_EHIP if the allocation, copy, capture or instantiation fails.
+ */
+int simplex_queue_graph_create(const struct simplex_job *jobs, int32_t njobs, int32_t max_workgroups,
+                               void **graph);
+
 /* ---- serving loop -------------------------------------------------------
  *
  * A request stream of automaton-step jobs (the continuous-batching serving

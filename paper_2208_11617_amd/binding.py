@@ -25,7 +25,7 @@ EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_autotune", "simplex_autotune_reset", "simplex_graph_create",
            "simplex_graph_launch", "simplex_graph_destroy", "simplex_map_launch_steps",
            "simplex_bb_launch_steps", "simplex_set_layout", "simplex_queue_launch",
-           "simplex_set_general")
+           "simplex_set_general", "simplex_queue_graph_create")
 
 LAYOUT_PACKED, LAYOUT_LEVELS = 0, 1
 GENERAL_FUSED, GENERAL_STREAMS = 0, 1
@@ -119,6 +119,9 @@ def lib():
     L.simplex_set_tile.restype = ci
     L.simplex_batch_launch.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, vp]
     L.simplex_batch_launch.restype = ci
+    L.simplex_queue_graph_create.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.POINTER(vp)]
+    L.simplex_queue_graph_create.restype = ci
     L.simplex_set_general.argtypes = [ci]
     L.simplex_set_general.restype = ci
     L.simplex_queue_launch.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_int32, vp]
@@ -327,6 +330,29 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class QueueGraph(Graph):
+    """One persistent work-queue launch over a fixed job set, captured as a
+    graph (simplex_queue_graph_create); replay with launch(), free with close()."""
+
+    def __init__(self, jobs, max_workgroups=0):   # pylint: disable=super-init-not-called
+        h = ctypes.c_void_p()
+        arr = _job_array(jobs)
+        _check(lib().simplex_queue_graph_create(arr, len(jobs), max_workgroups, ctypes.byref(h)),
+               "simplex_queue_graph_create")
+        self.handle = h
+
+
+def queue_graph_create_raw(jobs, njobs=None, max_workgroups=0) -> int:
+    """Status of simplex_queue_graph_create (the graph, if any, is destroyed)."""
+    h = ctypes.c_void_p()
+    arr = _job_array(jobs)
+    rc = lib().simplex_queue_graph_create(arr, len(jobs) if njobs is None else njobs, max_workgroups,
+                                          ctypes.byref(h))
+    if rc == OK and h:
+        lib().simplex_graph_destroy(h)
+    return rc
 
 
 def map_launch_steps(m, n, op, steps, buf_in, buf_out, r=0, beta=0, stream=None) -> None:

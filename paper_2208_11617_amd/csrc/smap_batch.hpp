@@ -130,6 +130,13 @@ __device__ __forceinline__ void queue_small_step(const Plan &P, const uint8_t *_
     }
 }
 
+// Clears `count` words (a graph's head counter before each replay: a kernel
+// node rather than a memset node).
+__global__ __launch_bounds__(64) void k_zero_words(uint32_t *__restrict__ p, uint32_t count)
+{
+    for (uint32_t i = threadIdx.x; i < count; i += 64) p[i] = 0u;
+}
+
 __global__ __launch_bounds__(kQueueThreads) void k_queue(uint32_t *__restrict__ head,
                                                          const uint32_t *__restrict__ start,
                                                          const QueueJob *__restrict__ jobs, uint32_t njobs,

@@ -467,7 +467,9 @@ int do_launch(int m, int64_t n, int r, int beta, int op, const void *in, void *o
         std::lock_guard<std::mutex> lk(g_mu);
         general = g_general;
     }
-    if (!bb && general == 1 && P.npieces > 1)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (general == 1 && hipStreamIsCapturing(s, &cap) != hipSuccess) return kEhip;
+    if (!bb && general == 1 && P.npieces > 1 && cap == hipStreamCaptureStatusNone)
         rc = launch_pieces(m, op, tc, P, in, out, s);
     else
         rc = bb ? dispatch<true>(m, op, tc, P, in, out, s) : dispatch<false>(m, op, tc, P, in, out, s);
@@ -781,18 +783,18 @@ int launch_queue_chunk(BatchRing &R, const BatchItem *items, const uint32_t *kin
     return kOk;
 }
 
-int queue_launch(const simplex_job *jobs, int32_t njobs, int32_t max_wg, void *stream)
+// Validated work items of the queue kernel for jobs[0..njobs) (g_mu taken here).
+int queue_items(const simplex_job *jobs, int32_t njobs, std::vector<BatchItem> &items,
+                std::vector<uint32_t> &kinds)
 {
-    if (njobs < 0 || (njobs > 0 && !jobs) || max_wg < 0) return kEinval;
-    if (njobs == 0) return kOk;
     constexpr TileCfg kQ2 = {kQueueCa2Rho, kQueueThreads, 1};
     constexpr TileCfg kQ3 = {kQueueCa3Rho, kQueueThreads,
                              (kQueueCa3Rho / kQueueCa3Ry) * (kQueueCa3Rho / kQueueCa3Rz)};
     static_assert(Ca2Walk<kQueueCa2Rho, kQueueCa2W, kQueueCa2R>::SUB == kQ2.sub &&
                   Ca3Walk<kQueueCa3Rho, kQueueCa3Ry, kQueueCa3Rz, kQueueCa3Rl>::SUB == kQ3.sub,
                   "queue tile configurations disagree with the kernel");
-    std::vector<BatchItem> items;
-    std::vector<uint32_t> kinds;
+    items.clear();
+    kinds.clear();
     items.reserve((size_t)njobs);
     kinds.reserve((size_t)njobs);
     {
@@ -817,9 +819,49 @@ int queue_launch(const simplex_job *jobs, int32_t njobs, int32_t max_wg, void *s
             kinds.push_back(small ? (ca2 ? kQueueCa2Small : kQueueCa3Small) : (ca2 ? kQueueCa2 : kQueueCa3));
         }
     }
+    return kOk;
+}
+
+// The device-side table of one queue launch: head counter (zero), unit
+// prefix sums, jobs.  Returns its size; fills `h` (bytes, 256-aligned
+// sections) and the offsets of its parts.
+size_t queue_table(const BatchItem *items, const uint32_t *kinds, int cnt, std::vector<uint8_t> &h,
+                   size_t *start_off, size_t *jobs_off, uint64_t *units)
+{
+    constexpr size_t head_bytes = 256;
+    const size_t start_bytes = ((sizeof(uint32_t) * (size_t)(cnt + 1) + 255) / 256) * 256;
+    const size_t bytes = ((head_bytes + start_bytes + sizeof(QueueJob) * (size_t)cnt + 255) / 256) * 256;
+    h.assign(bytes, 0);
+    uint32_t *start = reinterpret_cast<uint32_t *>(h.data() + head_bytes);
+    QueueJob *jobs = reinterpret_cast<QueueJob *>(h.data() + head_bytes + start_bytes);
+    uint64_t acc = 0;
+    for (int i = 0; i < cnt; ++i) {
+        start[i] = (uint32_t)acc;
+        jobs[i].P = items[i].P;
+        jobs[i].in = items[i].in;
+        jobs[i].out = items[i].out;
+        jobs[i].kind = kinds[i];
+        jobs[i].reserved = 0;
+        acc += items[i].nwg;
+    }
+    start[cnt] = (uint32_t)acc;
+    *start_off = head_bytes;
+    *jobs_off = head_bytes + start_bytes;
+    *units = acc;
+    return bytes;
+}
+
+int queue_launch(const simplex_job *jobs, int32_t njobs, int32_t max_wg, void *stream)
+{
+    if (njobs < 0 || (njobs > 0 && !jobs) || max_wg < 0) return kEinval;
+    if (njobs == 0) return kOk;
+    std::vector<BatchItem> items;
+    std::vector<uint32_t> kinds;
+    int rc = queue_items(jobs, njobs, items, kinds);
+    if (rc != kOk) return rc;
     std::lock_guard<std::mutex> lk(g_batch_mu);
     BatchRing *R = nullptr;
-    int rc = ring_for_device(&R);
+    rc = ring_for_device(&R);
     if (rc != kOk) return rc;
     for (size_t o = 0; o < items.size(); o += kBatchMaxJobs) {
         const int cnt = (int)std::min<size_t>(kBatchMaxJobs, items.size() - o);
@@ -962,7 +1004,71 @@ int autotune(int m, int64_t n, int op, const void *in, void *out, int32_t reps, 
 struct GraphHandle {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    void *table = nullptr;   // device memory the graph's kernels read (queue graphs)
 };
+
+// One persistent work-queue launch over a fixed job set, captured as a
+// graph: a fill kernel clears the head counter (no memset node), then the
+// queue kernel runs; the job table lives in device memory the graph owns.
+int queue_graph_create(const simplex_job *jobs, int32_t njobs, int32_t max_wg, void **handle)
+{
+    if (!handle || njobs < 1 || !jobs || max_wg < 0) return kEinval;
+    *handle = nullptr;
+    if (njobs > kBatchMaxJobs) return kErange;
+    std::vector<BatchItem> items;
+    std::vector<uint32_t> kinds;
+    int rc = queue_items(jobs, njobs, items, kinds);
+    if (rc != kOk) return rc;
+    std::vector<uint8_t> h;
+    size_t start_off = 0, jobs_off = 0;
+    uint64_t units = 0;
+    const size_t bytes = queue_table(items.data(), kinds.data(), njobs, h, &start_off, &jobs_off, &units);
+    if (units == 0) return kEinval;
+    if (units > kMaxWorkgroups) return kErange;
+    uint32_t grid = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        rc = queue_grid_for_device(&grid);
+    }
+    if (rc != kOk) return rc;
+    if (max_wg > 0) grid = std::min(grid, (uint32_t)max_wg);
+    grid = (uint32_t)std::min<uint64_t>(grid, units);
+    GraphHandle *gh = new GraphHandle();
+    uint8_t *d = nullptr;
+    if (hipMalloc((void **)&d, bytes) != hipSuccess) {
+        delete gh;
+        return kEhip;
+    }
+    gh->table = d;
+    hipStream_t cs = nullptr;
+    rc = kOk;
+    if (hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) rc = kEhip;
+    if (rc == kOk && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) rc = kEhip;
+    if (rc == kOk && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = kEhip;
+    if (rc == kOk) {
+        uint32_t *head = reinterpret_cast<uint32_t *>(d);
+        hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, cs, head, 1u);
+        hipLaunchKernelGGL(k_queue, dim3(grid), dim3(kQueueThreads), 0, cs, head,
+                           reinterpret_cast<const uint32_t *>(d + start_off),
+                           reinterpret_cast<const QueueJob *>(d + jobs_off), (uint32_t)njobs, (uint32_t)units);
+        if (hipGetLastError() != hipSuccess) rc = kEhip;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (rc == kOk && e != hipSuccess) rc = kEhip;
+        gh->graph = g;
+        if (rc == kOk && hipGraphInstantiate(&gh->exec, g, nullptr, nullptr, 0) != hipSuccess) rc = kEhip;
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc != kOk) {
+        if (gh->exec) (void)hipGraphExecDestroy(gh->exec);
+        if (gh->graph) (void)hipGraphDestroy(gh->graph);
+        (void)hipFree(gh->table);
+        delete gh;
+        return rc;
+    }
+    *handle = gh;
+    return kOk;
+}
 
 int graph_create(int m, int64_t n, int r, int beta, int op, bool bb, const void *in, void *out,
                  int32_t steps, void **handle)
@@ -1260,6 +1366,12 @@ int simplex_graph_create(int m, int64_t n, int r, int beta, int op, int use_bb, 
     return graph_create(m, n, r, beta, op, use_bb != 0, buf_in, buf_out, steps, graph);
 }
 
+int simplex_queue_graph_create(const struct simplex_job *jobs, int32_t njobs, int32_t max_workgroups,
+                               void **graph)
+{
+    return queue_graph_create(jobs, njobs, max_workgroups, graph);
+}
+
 int simplex_graph_launch(void *graph, void *stream)
 {
     if (!graph) return kEinval;
@@ -1274,6 +1386,7 @@ int simplex_graph_destroy(void *graph)
     int rc = kOk;
     if (h->exec && hipGraphExecDestroy(h->exec) != hipSuccess) rc = kEhip;
     if (h->graph && hipGraphDestroy(h->graph) != hipSuccess) rc = kEhip;
+    if (h->table && hipFree(h->table) != hipSuccess) rc = kEhip;
     delete h;
     return rc;
 }

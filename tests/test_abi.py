@@ -146,6 +146,22 @@ def test_batch_launch_argument_errors():
     assert smap.batch_launch_raw([good, (2, "ca2", 100, 4096, 4096 + 50)]) == E  # overlap
 
 
+def test_queue_graph_argument_errors():
+    """simplex_queue_graph_create validates before any device work."""
+    import ctypes
+    E = smap.EINVAL
+    good = (2, "ca2", 100, 4096, 1 << 20)
+    assert smap.queue_graph_create_raw([], 0) == E                       # no jobs
+    assert smap.queue_graph_create_raw([good], max_workgroups=-1) == E
+    assert smap.queue_graph_create_raw([(2, "hash", 10, 4096, 1 << 20)]) == E   # automata only
+    assert smap.queue_graph_create_raw([good, (2, "ca2", 100, 4096, 4096 + 50)]) == E  # overlap
+    assert smap.queue_graph_create_raw([good] * 4097) == smap.ERANGE     # more than one launch takes
+    arr = smap._job_array([good])
+    assert smap.lib().simplex_queue_graph_create(arr, 1, 0, None) == E   # NULL graph
+    h = ctypes.c_void_p()
+    assert smap.lib().simplex_queue_graph_create(None, 1, 0, ctypes.byref(h)) == E
+
+
 def test_set_general_argument_errors():
     assert smap.lib().simplex_set_general(2) == smap.EINVAL
     assert smap.lib().simplex_set_general(-1) == smap.EINVAL

@@ -113,3 +113,34 @@ def test_graph_ca2_ping_pong_replays(smap, use_bb):
             assert torch.equal(a, ea) and torch.equal(b, eb), k
     finally:
         g.close()
+
+
+def test_queue_graph_replays(smap):
+    """A persistent work-queue launch over a fixed mix of CA2 and CA3 jobs,
+    captured once and replayed several times with eager work (output resets)
+    and synchronisations in between: every replay equals the single launches."""
+    OP = {2: "ca2", 3: "ca3"}
+    MIX = [(2, n) for n in (0, 5, 14, 15, 37, 256, 300, 2049)] + [(3, n) for n in (0, 3, 14, 16, 64, 65, 130)]
+    ins = [si.box_torch(m, n, "bern", 5700 + k, p=0.25 if m == 2 else 0.2, device="cuda")
+           for k, (m, n) in enumerate(MIX)]
+    refs = []
+    for k, (m, n) in enumerate(MIX):
+        ref = si.sentinel_box_torch(m, n, True, device="cuda")
+        smap.map_launch(m, n, OP[m], ins[k], ref)
+        refs.append(ref)
+    outs = [si.sentinel_box_torch(m, n, True, device="cuda") for m, n in MIX]
+    torch.cuda.synchronize()
+    for cap in (0, 7):
+        g = smap.QueueGraph([(m, OP[m], n, ins[k], outs[k]) for k, (m, n) in enumerate(MIX)], max_workgroups=cap)
+        try:
+            for rep in range(4):
+                for o in outs:
+                    o.fill_(si.SENTINEL_U8)
+                torch.cuda.synchronize()
+                say(f"queue graph cap={cap} replay {rep}")
+                g.launch(torch.cuda.current_stream())
+                torch.cuda.synchronize()
+                for k, (m, n) in enumerate(MIX):
+                    assert torch.equal(outs[k], refs[k]), (cap, rep, m, n)
+        finally:
+            g.close()
