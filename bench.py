@@ -47,16 +47,19 @@ def kernel_sha(op: str) -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload: str, op: str):
+def stored_traffic(workload: str, op: str, info: dict):
     """HBM bytes per launch of the H kernel from the committed rocprofv3
-    counter summary, or None when there is none or the kernel's sources
-    changed since the counters were taken."""
+    counter summary, or None when there is none, the kernel's sources
+    changed since the counters were taken, or the launch differs from the
+    one measured (tile side, and launched workgroups where recorded)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_sha") != kernel_sha(op):
+    if rec.get("kernel_sha") != kernel_sha(op) or rec.get("rho") != info["rho"]:
+        return None
+    if "launched_wgs" in rec and rec["launched_wgs"] != info["launched_wgs"]:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -351,7 +354,7 @@ def main():
                     help="time H as replays of a captured graph of this many launches")
     ap.add_argument("--general", default="fused", choices=["fused", "streams"],
                     help="H launches: all pieces in one launch, or one launch per piece on streams of their own")
-    ap.add_argument("--layout3", default="packed", choices=["packed", "levels"],
+    ap.add_argument("--layout3", default="auto", choices=["auto", "packed", "levels"],
                     help="native layout of the 3-D H map")
     ap.add_argument("--gens", type=int, default=0,
                     help="automata: time simplex_map_launch_steps advancing this many generations per call")
@@ -388,7 +391,8 @@ def main():
     stream = torch.cuda.current_stream()
     useful = smap.count(m, n)
     if m == 3:
-        smap.set_layout(3, smap.LAYOUT_LEVELS if args.layout3 == "levels" else smap.LAYOUT_PACKED)
+        smap.set_layout(3, {"auto": smap.LAYOUT_AUTO, "packed": smap.LAYOUT_PACKED,
+                            "levels": smap.LAYOUT_LEVELS}[args.layout3])
     smap.set_general(smap.GENERAL_STREAMS if args.general == "streams" else smap.GENERAL_FUSED)
 
     log(f"generating {args.workload}: m={m} n={n} op={op}")
@@ -489,7 +493,7 @@ def main():
     info_bb = smap.plan_info(m, n, op, use_bb=True)
     alg_bytes = useful * BYTES_PER_ELEMENT[op]        # per pass over HBM
     achieved = alg_bytes / (h_ms * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload, op) if args.gens == 0 else None
+    traffic = stored_traffic(args.workload, op, info_h) if args.gens == 0 else None
     value = useful * gens / (h_ms * 1e-3)             # useful cell updates per second
 
     res = {

@@ -165,8 +165,8 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
  *              on a 1024-byte column of the tile.
  *   Large tiles are split into sub-blocks of rows (and planes), one
  *   workgroup each (wgs_per_tile in the plan info).
- *   CA3 (m=3): rho 128 (256 threads; 128 or 512), 256 (256), 64 (128 or
- *              256), 32 (64).
+ *   CA3 (m=3): rho 256 (256 threads; the default), 128 (256; 128 or 512),
+ *              64 (128 or 256), 32 (64).
  * wg_threads = 0 picks the first listed size; any other value must be one
  * of the listed sizes.
  */
@@ -175,7 +175,10 @@ int simplex_set_tile(int m, int op, int rho, int wg_threads);
 /*
  * Layout of the native part of the 3-D H map for later launches of this
  * process (H launches, plans and plan info; BB is not affected):
- *   SMAP_LAYOUT_PACKED (default): the packed grid (N/2) x (N/2) x (N/2 + N/4)
+ *   SMAP_LAYOUT_AUTO (default): LEVELS for single CA3 launches (and their
+ *     plans and plan info), PACKED for the per-element ops and for the
+ *     batched, work-queue and multi-generation launches;
+ *   SMAP_LAYOUT_PACKED: the packed grid (N/2) x (N/2) x (N/2 + N/4)
  *     of Section 4.3, one launch, 1/8 of its workgroups discarded
  *     (launched / useful tiles of the native part -> 9/8);
  *   SMAP_LAYOUT_LEVELS: the fully efficient variant of Section 4.3 (one
@@ -185,6 +188,7 @@ int simplex_set_tile(int m, int op, int rho, int wg_threads);
  * Only m = 3 is accepted (others: SMAP_EINVAL); an unknown layout gives
  * SMAP_EINVAL.
  */
+#define SMAP_LAYOUT_AUTO (-1)
 #define SMAP_LAYOUT_PACKED 0
 #define SMAP_LAYOUT_LEVELS 1
 int simplex_set_layout(int m, int layout);

@@ -27,7 +27,7 @@ EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_bb_launch_steps", "simplex_set_layout", "simplex_queue_launch",
            "simplex_set_general", "simplex_queue_graph_create")
 
-LAYOUT_PACKED, LAYOUT_LEVELS = 0, 1
+LAYOUT_AUTO, LAYOUT_PACKED, LAYOUT_LEVELS = -1, 0, 1
 GENERAL_FUSED, GENERAL_STREAMS = 0, 1
 
 SERVE_SEQUENTIAL, SERVE_BATCHED, SERVE_PERSISTENT = 0, 1, 2
@@ -380,5 +380,6 @@ def set_general(strategy) -> None:
 
 
 def set_layout(m, layout) -> None:
-    """Native layout of the 3-D H map: LAYOUT_PACKED (default) or LAYOUT_LEVELS."""
+    """Native layout of the 3-D H map: LAYOUT_AUTO (default: levels for
+    single CA3 launches, packed otherwise), LAYOUT_PACKED or LAYOUT_LEVELS."""
     _check(lib().simplex_set_layout(m, layout), "simplex_set_layout")

@@ -80,7 +80,7 @@ int op_class(int op) { return op == OP_CA2 ? 1 : (op == OP_CA3 ? 2 : 0); }
 TileCfg default_tile(int m, int cls)
 {
     if (cls == 1) return {1024, 64, 64};
-    if (cls == 2) return {128, 256, (128 / 64) * (128 / ca3_rz(128))};
+    if (cls == 2) return {256, 256, (256 / 32) * (256 / ca3_rz(256))};
     for (const PointShape &c : kPointShapes)  // the first listed shape of an m is its default
         if (c.m == m) return {c.rho, c.wg, c.sub};
     return {0, 0, 1};
@@ -129,7 +129,10 @@ struct CachedPlan {
     int status;
 };
 std::map<std::tuple<int, int64_t, int, int, int, int, int>, CachedPlan> g_plans;  // (m,n,beta,rho,bb,cls,layout)
-int g_layout3 = 0;  // H native layout for m = 3 (simplex_set_layout)
+// H native layout for m = 3 (simplex_set_layout); SMAP_LAYOUT_AUTO: the
+// level-ordered layout for single CA3 launches and their plans, the packed
+// one for everything else
+int g_layout3 = SMAP_LAYOUT_AUTO;
 int g_general = 0;  // H launch of the pieces: 0 fused, 1 one launch per piece (simplex_set_general)
 
 TileCfg tile_for(int m, int cls)
@@ -178,9 +181,13 @@ bool box_elems(int m, int64_t n, int64_t *out)
 // Plan lookup; also checks that in-tile offsets fit the kernels' 32-bit
 // lane offsets.
 // Plan of (m, n, beta, tile t, H|BB, op class) from the cache (g_mu held).
-int plan_for(int m, int64_t n, int beta, bool bb, int cls, const TileCfg &t, Plan *P, PlanCounts *C)
+int plan_for(int m, int64_t n, int beta, bool bb, int cls, const TileCfg &t, Plan *P, PlanCounts *C,
+             bool single = false)
 {
-    const int lay = (m == 3 && !bb) ? g_layout3 : 0;
+    int lay = 0;
+    if (m == 3 && !bb)
+        lay = g_layout3 != SMAP_LAYOUT_AUTO ? g_layout3
+                                            : (single && cls == 2 ? SMAP_LAYOUT_LEVELS : SMAP_LAYOUT_PACKED);
     auto key = std::make_tuple(m, n, bb ? 0 : beta, t.rho, bb ? 1 : 0, cls, lay);
     auto it = g_plans.find(key);
     if (it == g_plans.end()) {
@@ -223,7 +230,7 @@ int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C
     std::lock_guard<std::mutex> lk(g_mu);
     const TileCfg t = bb ? tile_for(m, cls) : tile_for_h(m, n, cls);
     *tc = t;
-    return plan_for(m, n, beta, bb, cls, t, P, C);
+    return plan_for(m, n, beta, bb, cls, t, P, C, true);
 }
 
 int check_op(int m, int64_t n, int op)
@@ -1413,7 +1420,8 @@ int simplex_set_general(int strategy)
 
 int simplex_set_layout(int m, int layout)
 {
-    if (m != 3 || (layout != SMAP_LAYOUT_PACKED && layout != SMAP_LAYOUT_LEVELS)) return kEinval;
+    if (m != 3 || (layout != SMAP_LAYOUT_AUTO && layout != SMAP_LAYOUT_PACKED && layout != SMAP_LAYOUT_LEVELS))
+        return kEinval;
     std::lock_guard<std::mutex> lk(g_mu);
     g_layout3 = layout;
     return kOk;

@@ -370,7 +370,7 @@ def test_levels_layout_3d(smap):
     finally:
         smap.set_tile(3, "hits", 0)
         smap.set_tile(3, "ca3", 0)
-        smap.set_layout(3, smap.LAYOUT_PACKED)
+        smap.set_layout(3, smap.LAYOUT_AUTO)
 
 
 # ---- the pieces as concurrent launches (Section 4.2's concurrent trapezoids)

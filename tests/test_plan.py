@@ -221,7 +221,7 @@ def test_levels_layout_3d_covers_exactly_once_without_waste():
         assert lev["useful_tiles"] == pk["useful_tiles"] and lev["launched_tiles"] < pk["launched_tiles"]
     finally:
         smap.set_tile(3, "hits", 0)
-        smap.set_layout(3, smap.LAYOUT_PACKED)
+        smap.set_layout(3, smap.LAYOUT_AUTO)
     with pytest.raises(smap.SimplexMapError):
         smap.set_layout(2, smap.LAYOUT_LEVELS)
     with pytest.raises(smap.SimplexMapError):
@@ -255,3 +255,20 @@ def test_concurrent_plan_queries_match_sequential():
         t.join()
     assert not errors, errors[0]
     assert got == want
+
+
+def test_auto_layout_levels_for_single_ca3_launches_only():
+    """By default single CA3 launches (and their plan info) use the
+    level-ordered layout at rho 256, the per-element ops the packed one."""
+    assert smap.plan_info(3, 1024, "ca3")["rho"] == 256
+    auto_ca3, auto_hits = smap.plan_info(3, 1024, "ca3"), smap.plan_info(3, 1024, "hits")
+    try:
+        smap.set_layout(3, smap.LAYOUT_LEVELS)
+        assert smap.plan_info(3, 1024, "ca3") == auto_ca3
+        smap.set_layout(3, smap.LAYOUT_PACKED)
+        assert smap.plan_info(3, 1024, "hits") == auto_hits
+        assert smap.plan_info(3, 1024, "ca3")["launched_tiles"] > auto_ca3["launched_tiles"]
+    finally:
+        smap.set_layout(3, smap.LAYOUT_AUTO)
+    for n in (0, 1, 255, 256, 511, 700):
+        check_exact(3, n, "ca3")
