@@ -510,7 +510,8 @@ def main():
         "dtype": "u8" if u8 else "u32",
         "data": "synthetic (seeded splitmix64)",
         "config": {"workload": f"{args.workload}: m={m} n={n} op={op}", "m": m, "n": n,
-                   "op": op, "useful_elements": useful, "rho": info_h["rho"],
+                   "op": op, "useful_elements": useful,
+                   "rho": info_h["rho"] if args.gens == 0 else (256 if m == 2 else 64),
                    "beta": info_h["beta"], "autotuned": tuned, "graph_launches": args.graph or None,
                    "generations_per_call": gens, "layout3": args.layout3 if m == 3 else None,
                    "general": args.general},
@@ -521,9 +522,12 @@ def main():
         "h_vs_bb_speedup": None if bb_ms is None else bb_ms / h_ms,
         "timing": {"h": h_stats or None, "bb": bb_stats or None},
         "best_vs_best": None if not sweep else best_vs_best(sweep),
-        "tiles": {"useful": info_h["useful_tiles"], "h_launched": info_h["launched_tiles"],
-                  "bb_launched": info_bb["launched_tiles"], "wgs_per_tile": info_h["wgs_per_tile"],
-                  "h_workgroups": info_h["launched_wgs"], "bb_workgroups": info_bb["launched_wgs"]},
+        # (plan info describes the one-step launch; the multi-generation
+        # kernels have tiles of their own)
+        "tiles": None if args.gens else {
+            "useful": info_h["useful_tiles"], "h_launched": info_h["launched_tiles"],
+            "bb_launched": info_bb["launched_tiles"], "wgs_per_tile": info_h["wgs_per_tile"],
+            "h_workgroups": info_h["launched_wgs"], "bb_workgroups": info_bb["launched_wgs"]},
         "roofline": {
             "bound": "hbm" if op != "map" else "alu",
             "achieved": achieved,

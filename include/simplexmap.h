@@ -175,9 +175,9 @@ int simplex_set_tile(int m, int op, int rho, int wg_threads);
 /*
  * Layout of the native part of the 3-D H map for later launches of this
  * process (H launches, plans and plan info; BB is not affected):
- *   SMAP_LAYOUT_AUTO (default): LEVELS for single CA3 launches (and their
- *     plans and plan info), PACKED for the per-element ops and for the
- *     batched, work-queue and multi-generation launches;
+ *   SMAP_LAYOUT_AUTO (default): LEVELS for one-job CA3 launches (one step
+ *     or several generations, their plans and plan info), PACKED for the
+ *     per-element ops and for the batched and work-queue launches;
  *   SMAP_LAYOUT_PACKED: the packed grid (N/2) x (N/2) x (N/2 + N/4)
  *     of Section 4.3, one launch, 1/8 of its workgroups discarded
  *     (launched / useful tiles of the native part -> 9/8);

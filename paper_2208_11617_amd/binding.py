@@ -381,5 +381,5 @@ def set_general(strategy) -> None:
 
 def set_layout(m, layout) -> None:
     """Native layout of the 3-D H map: LAYOUT_AUTO (default: levels for
-    single CA3 launches, packed otherwise), LAYOUT_PACKED or LAYOUT_LEVELS."""
+    one-job CA3 launches, packed otherwise), LAYOUT_PACKED or LAYOUT_LEVELS."""
     _check(lib().simplex_set_layout(m, layout), "simplex_set_layout")

@@ -130,8 +130,8 @@ struct CachedPlan {
 };
 std::map<std::tuple<int, int64_t, int, int, int, int, int>, CachedPlan> g_plans;  // (m,n,beta,rho,bb,cls,layout)
 // H native layout for m = 3 (simplex_set_layout); SMAP_LAYOUT_AUTO: the
-// level-ordered layout for single CA3 launches and their plans, the packed
-// one for everything else
+// level-ordered layout for one-job CA3 launches (one step or several
+// generations) and their plans, the packed one for everything else
 int g_layout3 = SMAP_LAYOUT_AUTO;
 int g_general = 0;  // H launch of the pieces: 0 fused, 1 one launch per piece (simplex_set_general)
 
@@ -182,12 +182,12 @@ bool box_elems(int m, int64_t n, int64_t *out)
 // lane offsets.
 // Plan of (m, n, beta, tile t, H|BB, op class) from the cache (g_mu held).
 int plan_for(int m, int64_t n, int beta, bool bb, int cls, const TileCfg &t, Plan *P, PlanCounts *C,
-             bool single = false)
+             bool one_job = false)
 {
     int lay = 0;
     if (m == 3 && !bb)
         lay = g_layout3 != SMAP_LAYOUT_AUTO ? g_layout3
-                                            : (single && cls == 2 ? SMAP_LAYOUT_LEVELS : SMAP_LAYOUT_PACKED);
+                                            : (one_job && cls == 2 ? SMAP_LAYOUT_LEVELS : SMAP_LAYOUT_PACKED);
     auto key = std::make_tuple(m, n, bb ? 0 : beta, t.rho, bb ? 1 : 0, cls, lay);
     auto it = g_plans.find(key);
     if (it == g_plans.end()) {
@@ -1142,7 +1142,7 @@ int steps_launch(int m, int64_t n, int r, int beta, int op, int32_t steps, void 
     Plan P;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        rc = plan_for(m, n, bt, bb, ca3 ? 2 : 1, ca3 ? kSteps3Tile : kStepsTile, &P, nullptr);
+        rc = plan_for(m, n, bt, bb, ca3 ? 2 : 1, ca3 ? kSteps3Tile : kStepsTile, &P, nullptr, true);
     }
     if (rc != kOk) return rc;
     if (P.total == 0) return kOk;
