@@ -188,6 +188,11 @@ def copy_probe(nbytes, steps, stream):
             "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def set_layout3(smap, name):
+    smap.set_layout(3, {"auto": smap.LAYOUT_AUTO, "packed": smap.LAYOUT_PACKED,
+                        "levels": smap.LAYOUT_LEVELS}[name])
+
+
 def bench_serve(args):
     """The serving workload: a stream of one-step automaton jobs (60 % m = 2
     with n log-uniform in [64, 4096], 40 % m = 3 with n log-uniform in
@@ -205,6 +210,7 @@ def bench_serve(args):
     import simplex_inputs as si
     from paper_2208_11617_amd import binding as smap
 
+    set_layout3(smap, args.layout3)
     torch.cuda.set_device(0)
     jobs0 = si.serve_trace(args.jobs, None)
     shapes = sorted(set((m, n) for m, n, _ in jobs0))
@@ -257,7 +263,8 @@ def bench_serve(args):
         "config": {"workload": f"c5: serving, {args.jobs} one-step automaton jobs, "
                                f"{len(shapes)} sizes, budget {args.budget_gib} GiB",
                    "jobs": args.jobs, "budget_gib": args.budget_gib, "load": args.load,
-                   "offered_rate_jobs_per_s": rate, "max_inflight": args.max_inflight},
+                   "offered_rate_jobs_per_s": rate, "max_inflight": args.max_inflight,
+                   "layout3": args.layout3},
         "serving": res,
         "batched_vs_sequential_saturated": sat_b["jobs_per_s"] / res["saturated_sequential"]["jobs_per_s"],
         "persistent_vs_sequential_saturated":
@@ -391,8 +398,7 @@ def main():
     stream = torch.cuda.current_stream()
     useful = smap.count(m, n)
     if m == 3:
-        smap.set_layout(3, {"auto": smap.LAYOUT_AUTO, "packed": smap.LAYOUT_PACKED,
-                            "levels": smap.LAYOUT_LEVELS}[args.layout3])
+        set_layout3(smap, args.layout3)
     smap.set_general(smap.GENERAL_STREAMS if args.general == "streams" else smap.GENERAL_FUSED)
 
     log(f"generating {args.workload}: m={m} n={n} op={op}")
