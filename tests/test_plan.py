@@ -226,6 +226,10 @@ def test_levels_layout_3d_covers_exactly_once_without_waste():
         smap.set_layout(2, smap.LAYOUT_LEVELS)
     with pytest.raises(smap.SimplexMapError):
         smap.set_layout(3, 7)
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_layout(3, -2)
+    with pytest.raises(smap.SimplexMapError):
+        smap.set_layout(2, smap.LAYOUT_AUTO)
 
 
 def test_concurrent_plan_queries_match_sequential():
