@@ -77,10 +77,17 @@ constexpr Ca3Shape kCa3Shapes[] = {
 // op class: 0 = pointwise (MAP/ACCUM/HITS/HASH), 1 = CA2, 2 = CA3
 int op_class(int op) { return op == OP_CA2 ? 1 : (op == OP_CA3 ? 2 : 0); }
 
-TileCfg default_tile(int m, int cls)
+// CA3: 256^3 tiles from n = 768 on; below, 128^3 (with only two or three
+// 256-cell tiles per side most of their sub-blocks fall outside the simplex)
+constexpr int64_t kCa3LargeTileN = 768;
+
+TileCfg default_tile(int m, int64_t n, int cls)
 {
     if (cls == 1) return {1024, 64, 64};
-    if (cls == 2) return {256, 256, (256 / 32) * (256 / ca3_rz(256))};
+    if (cls == 2) {
+        if (n >= kCa3LargeTileN) return {256, 256, (256 / 32) * (256 / ca3_rz(256))};
+        return {128, 256, (128 / 64) * (128 / ca3_rz(128))};
+    }
     for (const PointShape &c : kPointShapes)  // the first listed shape of an m is its default
         if (c.m == m) return {c.rho, c.wg, c.sub};
     return {0, 0, 1};
@@ -135,10 +142,10 @@ std::map<std::tuple<int, int64_t, int, int, int, int, int>, CachedPlan> g_plans;
 int g_layout3 = SMAP_LAYOUT_AUTO;
 int g_general = 0;  // H launch of the pieces: 0 fused, 1 one launch per piece (simplex_set_general)
 
-TileCfg tile_for(int m, int cls)
+TileCfg tile_for(int m, int64_t n, int cls)
 {
     auto it = g_tiles.find({m, cls});
-    return it != g_tiles.end() ? it->second : default_tile(m, cls);
+    return it != g_tiles.end() ? it->second : default_tile(m, n, cls);
 }
 
 // Autotuned H choices per (m, n, op class) (g_mu held when used).
@@ -151,7 +158,7 @@ std::map<std::tuple<int, int64_t, int>, Tuned> g_tuned;
 TileCfg tile_for_h(int m, int64_t n, int cls)
 {
     auto it = g_tuned.find(std::make_tuple(m, n, cls));
-    return it != g_tuned.end() ? it->second.t : tile_for(m, cls);
+    return it != g_tuned.end() ? it->second.t : tile_for(m, n, cls);
 }
 
 int resolve_rb(int m, int r, int beta, int *beta_out)
@@ -228,7 +235,7 @@ int get_plan(int m, int64_t n, int beta, int op, bool bb, Plan *P, PlanCounts *C
 {
     const int cls = op_class(op);
     std::lock_guard<std::mutex> lk(g_mu);
-    const TileCfg t = bb ? tile_for(m, cls) : tile_for_h(m, n, cls);
+    const TileCfg t = bb ? tile_for(m, n, cls) : tile_for_h(m, n, cls);
     *tc = t;
     return plan_for(m, n, beta, bb, cls, t, P, C, true);
 }

@@ -265,6 +265,10 @@ def test_auto_layout_levels_for_single_ca3_launches_only():
     """By default single CA3 launches (and their plan info) use the
     level-ordered layout at rho 256, the per-element ops the packed one."""
     assert smap.plan_info(3, 1024, "ca3")["rho"] == 256
+    # the default CA3 tile: 128^3 below n = 768, 256^3 from there on (H and BB)
+    for n, rho in ((0, 128), (500, 128), (767, 128), (768, 256), (2000, 256)):
+        assert smap.plan_info(3, n, "ca3")["rho"] == rho, n
+        assert smap.plan_info(3, n, "ca3", use_bb=True)["rho"] == rho, n
     auto_ca3, auto_hits = smap.plan_info(3, 1024, "ca3"), smap.plan_info(3, 1024, "hits")
     try:
         smap.set_layout(3, smap.LAYOUT_LEVELS)
