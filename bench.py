@@ -1,11 +1,14 @@
 """Benchmark: useful simplex elements/s of one step of the hot path, H vs BB.
 
-Default workload (the 2-D automaton step the metric is quoted on):
-m = 2, n = 16384, one Life step B3/S23 on uint8 cells, Bernoulli(0.3),
-(n+1)^2 box, ping-pong between two device-resident buffers.  A step is one
-launch of the whole path (plan lookup, H decode, tile walk, op).
+Default workload (the largest configuration that fits one GPU): m = 3,
+n = 1024, one step of the 3-D automaton B6/S567 on uint8 cells,
+Bernoulli(0.2), (n+1)^3 box (1.08 GB per buffer), ping-pong between two
+device-resident buffers.  A step is one launch of the whole path (plan
+lookup, H decode, tile walk, op).  The other workloads (c1 m = 2 n = 1024
+ACCUM, c2 m = 2 n = 16384 Life, c4 m = 4 n = 128 HASH, c5 serving) are
+selected with --workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
                     [--no-cpu] [--no-bb]
 
 Prints ONE JSON line on stdout; progress goes to stderr.
@@ -32,6 +35,7 @@ KERNEL_SOURCES = {
     "ca2": ["smap_decode.hpp", "smap_ca2.hpp"],
     "ca3": ["smap_decode.hpp", "smap_ca2.hpp", "smap_ca3.hpp"],
     "point": ["smap_decode.hpp", "smap_point.hpp"],
+    "copy": ["smap_copy.hpp"],
 }
 
 
@@ -57,18 +61,38 @@ def stored_traffic(workload: str, op: str, info: dict):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_sha") != kernel_sha(op) or rec.get("rho") != info["rho"]:
+    if rec.get("kernel_sha") != kernel_sha(op):
         return None
-    if "launched_wgs" in rec and rec["launched_wgs"] != info["launched_wgs"]:
-        return None
+    if info is not None:
+        if rec.get("rho") != info["rho"]:
+            return None
+        if "launched_wgs" in rec and rec["launched_wgs"] != info["launched_wgs"]:
+            return None
     return rec.get("hbm_bytes_per_launch")
 
 
-def time_launches(fn, steps, warmup, stream, stats=None, batches=10):
-    """Mean ms per launch over `steps` back-to-back launches (HIP events on
-    `stream`).  With a dict `stats`, events between `batches` equal batches
-    of the same timed region also give the median, mean and standard error
-    of the per-batch means (ms per launch)."""
+def _batch_stats(per):
+    """Median, mean and standard error of the mean of per-batch means."""
+    nb = len(per)
+    per = sorted(per)
+    mean = sum(per) / nb
+    sem = (sum((x - mean) ** 2 for x in per) / (nb - 1) / nb) ** 0.5 if nb > 1 else None
+    mid = per[nb // 2] if nb % 2 else 0.5 * (per[nb // 2 - 1] + per[nb // 2])
+    return {"batches": nb, "median_ms": mid, "mean_ms": mean, "sem_ms": sem,
+            "sem_rel": None if sem is None else sem / mean}
+
+
+def time_launches(fn, steps, warmup, stream, stats=None, batches=10, sem_target=0.01, extra_s=10.0):
+    """Mean ms per launch over exactly `steps` back-to-back launches (HIP
+    events on `stream`); that figure is the one returned.
+
+    With a dict `stats`, the timed region is cut into `batches` equal
+    batches, and the median, mean and standard error of the per-batch
+    means (ms per launch) go into `stats`.  If the standard error is then
+    not below `sem_target` of the mean (the measurement protocol: repeat
+    until it is), further batches of the same size are timed after the
+    region, for at most `extra_s` seconds, and the statistics cover all of
+    them (`converged` says whether the target was reached)."""
     import torch
     for i in range(warmup):
         fn(i)
@@ -82,14 +106,27 @@ def time_launches(fn, steps, warmup, stream, stats=None, batches=10):
             fn(warmup + i)
         evs[b + 1].record(stream)
     torch.cuda.synchronize()
+    ms = evs[0].elapsed_time(evs[-1]) / steps      # ms per launch over the K timed steps
     if stats is not None:
-        per = sorted(evs[b].elapsed_time(evs[b + 1]) / (cuts[b + 1] - cuts[b]) for b in range(nb))
-        mean = sum(per) / nb
-        sem = (sum((x - mean) ** 2 for x in per) / (nb - 1) / nb) ** 0.5 if nb > 1 else None
-        mid = per[nb // 2] if nb % 2 else 0.5 * (per[nb // 2 - 1] + per[nb // 2])
-        stats.update(batches=nb, median_ms=mid, mean_ms=mean, sem_ms=sem,
-                     sem_rel=None if sem is None else sem / mean)
-    return evs[0].elapsed_time(evs[-1]) / steps  # ms per launch
+        per = [evs[b].elapsed_time(evs[b + 1]) / (cuts[b + 1] - cuts[b]) for b in range(nb)]
+        st = _batch_stats(per)
+        size = max(1, steps // nb)
+        t0 = time.perf_counter()
+        i = warmup + steps
+        while (st["sem_rel"] is None or st["sem_rel"] >= sem_target) and time.perf_counter() - t0 < extra_s:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(size):
+                fn(i)
+                i += 1
+            e1.record(stream)
+            torch.cuda.synchronize()
+            per.append(e0.elapsed_time(e1) / size)
+            st = _batch_stats(per)
+        st["timed_steps_ms"] = ms
+        st["converged"] = st["sem_rel"] is not None and st["sem_rel"] < sem_target
+        stats.update(st)
+    return ms
 
 
 def tile_sweep(m, op, fn_for, steps, warmup, stream):
@@ -186,6 +223,18 @@ def copy_probe(nbytes, steps, stream):
     del src, dst
     return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms,
             "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
+def simplex_copy_probe(smap, m, n, src, dst, steps, stream):
+    """The copy of just the simplex cells (simplex_copy_launch): one read and
+    one write per simplex cell, row by row, no tiles and no halo -- the
+    floor the (n+1)^m layout puts on one pass over the simplex.  Its HBM
+    counters, when stored for this workload, come with it."""
+    useful = smap.count(m, n)
+    stats = {}
+    ms = time_launches(lambda i: smap.copy_launch(m, n, src, dst, stream=stream), steps, 3, stream, stats)
+    return {"ms": ms, "bytes_algorithmic": 2 * useful, "gbs": 2 * useful / (ms * 1e-3) / 1e9,
+            "frac_of_peak": 2 * useful / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "timing": stats}
 
 
 def set_layout3(smap, name):
@@ -342,7 +391,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--jobs", type=int, default=10000, help="c5: jobs in the stream")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="c5: output arena")
     ap.add_argument("--load", type=float, default=0.8, help="c5: offered load / sequential rate")
@@ -350,7 +399,7 @@ def main():
     ap.add_argument("--warmup-replays", type=int, default=1, help="c5: untimed replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg")
     ap.add_argument("--no-bb", action="store_true", help="skip timing the BB baseline")
-    ap.add_argument("--no-copy", action="store_true", help="skip the plain-copy probe")
+    ap.add_argument("--no-copy", action="store_true", help="skip the plain-copy and simplex-copy probes")
     ap.add_argument("--beta", type=int, default=0)
     ap.add_argument("--power", type=float, default=0.0,
                     help="also run H and BB for this many seconds each while sampling socket power (amd-smi)")
@@ -491,9 +540,14 @@ def main():
                            "elements_per_joule": None if not b_w else useful * gens * b_rate / b_w}
 
     copy = None
+    scopy = None
     if not args.no_copy:
         log("timing a plain copy of the same byte count")
         copy = copy_probe(max(useful * BYTES_PER_ELEMENT[op] // 2, 1 << 20), 20, stream)
+        if u8 and m in (2, 3):
+            log("timing the copy of just the simplex cells")
+            scopy = simplex_copy_probe(smap, m, n, bufs[0], out_a, max(20, args.steps // 4), stream)
+            scopy["traffic"] = stored_traffic(f"copy_{args.workload}", "copy", None)
 
     info_h = smap.plan_info(m, n, op, beta=tuned["beta"] if tuned else args.beta)
     info_bb = smap.plan_info(m, n, op, use_bb=True)
@@ -548,8 +602,11 @@ def main():
             "bytes_per_launch": alg_bytes,
             "copy_gbs": None if copy is None else copy["gbs"],
             "frac_of_copy": None if copy is None else achieved / copy["gbs"],
+            "simplex_copy_gbs": None if scopy is None else scopy["gbs"],
+            "frac_of_simplex_copy": None if scopy is None else achieved / scopy["gbs"],
         },
         "copy": copy,
+        "simplex_copy": scopy,
         "power": power,
         "cpu_baseline": None,
     }

@@ -275,6 +275,22 @@ int simplex_graph_destroy(void *graph);
 /* Static, human-readable text for a status code. */
 const char *simplex_strerror(int status);
 
+/*
+ * Measurement probe (no operation of the paper): copies the simplex cells of
+ * a uint8 (n+1)^m box, m = 2 or 3, from buf_in to buf_out, row by row (the
+ * cells x_1 = 0 .. n - (x_2 + ... + x_m) of each row are contiguous), with
+ * no tiles, no halo and no map.  It moves exactly the bytes of one automaton
+ * step (Section 5.1: one read and one write per simplex cell), so its time
+ * is the floor that the bounding-box layout puts on one pass over the
+ * simplex.  Cells outside the simplex are neither read nor written.
+ *   buf_in, buf_out: device pointers to (n+1)^m bytes, not overlapping.
+ * Enqueues on `stream` and returns without synchronising.  Errors:
+ * SMAP_EINVAL for m not in {2, 3}, n < 0, a NULL or overlapping buffer;
+ * SMAP_ERANGE for boxes beyond the index range; SMAP_EHIP for a launch
+ * failure.
+ */
+int simplex_copy_launch(int m, int64_t n, const void *buf_in, void *buf_out, void *stream);
+
 /* ---- several generations per launch -------------------------------------
  *
  * `steps` generations of the automaton (Section 5.1 runs a fixed number of

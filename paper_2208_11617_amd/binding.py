@@ -25,7 +25,7 @@ EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_autotune", "simplex_autotune_reset", "simplex_graph_create",
            "simplex_graph_launch", "simplex_graph_destroy", "simplex_map_launch_steps",
            "simplex_bb_launch_steps", "simplex_set_layout", "simplex_queue_launch",
-           "simplex_set_general", "simplex_queue_graph_create")
+           "simplex_set_general", "simplex_queue_graph_create", "simplex_copy_launch")
 
 LAYOUT_AUTO, LAYOUT_PACKED, LAYOUT_LEVELS = -1, 0, 1
 GENERAL_FUSED, GENERAL_STREAMS = 0, 1
@@ -34,9 +34,9 @@ SERVE_SEQUENTIAL, SERVE_BATCHED, SERVE_PERSISTENT = 0, 1, 2
 
 
 class SimplexMapError(RuntimeError):
-    def __init__(self, status: int, what: str):
+    def __init__(self, status: int, what: str, detail: str | None = None):
         self.status = status
-        super().__init__(f"{what}: {strerror(status)} (status {status})")
+        super().__init__(f"{what}: {detail or strerror(status)} (status {status})")
 
 
 class PlanInfo(ctypes.Structure):
@@ -146,6 +146,8 @@ def lib():
     L.simplex_bb_launch_steps.restype = ci
     L.simplex_set_layout.argtypes = [ci, ci]
     L.simplex_set_layout.restype = ci
+    L.simplex_copy_launch.argtypes = [ci, i64, vp, vp, vp]
+    L.simplex_copy_launch.restype = ci
     L.simplex_strerror.argtypes = [ci]
     L.simplex_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -169,6 +171,55 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+# Element types the kernels read and write, per op (torch dtype names).
+_U8 = ("uint8",)
+_W32 = ("int32", "uint32", "float32")
+_OP_DTYPES = {OP_ACCUM: (_W32, _W32), OP_HITS: (None, _W32), OP_HASH: (None, _W32),
+              OP_CA2: (_U8, _U8), OP_CA3: (_U8, _U8), OP_EDM: (("float32",), _W32)}
+
+
+def _need_bytes(op, m, n, which):
+    """Bytes the kernels may touch in buffer `which` (0 in, 1 out)."""
+    box = (n + 1) ** m
+    if op in (OP_CA2, OP_CA3):
+        return box
+    if op == OP_EDM and which == 0:
+        return 12 * (n + 1)                      # n+1 points in R^3, float32
+    return 4 * box
+
+
+def _check_tensor(t, what, dtypes, nbytes, role, device=True):
+    """Raise SimplexMapError(EINVAL) unless t is a contiguous device tensor of
+    one of `dtypes` holding at least `nbytes` bytes.  Runs before any call
+    into the library, so a wrong buffer never reaches a kernel."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise SimplexMapError(EINVAL, what, f"{role} must be a torch tensor, got {type(t).__name__}")
+    if str(t.dtype).replace("torch.", "") not in dtypes:
+        raise SimplexMapError(EINVAL, what, f"{role} has dtype {t.dtype}; expected one of {dtypes}")
+    if not t.is_contiguous():
+        raise SimplexMapError(EINVAL, what, f"{role} must be contiguous")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise SimplexMapError(EINVAL, what, f"{role} holds {have} bytes; the launch needs {nbytes}")
+    if device and not t.is_cuda:
+        raise SimplexMapError(EINVAL, what, f"{role} must be a device (cuda) tensor")
+
+
+def _check_op_buffers(what, m, n, op, buf_in, buf_out):
+    """Validate the tensors of one launch of `op` over Delta_n^m.  Sizes and
+    arguments the library itself rejects (m, n, op) are left to it."""
+    op = _op(op)
+    if op not in _OP_DTYPES or not isinstance(m, int) or not isinstance(n, int) or m < 2 or m > 4 or n < 0:
+        return
+    din, dout = _OP_DTYPES[op]
+    bufs = [(t, dt, which, role) for t, dt, which, role in
+            ((buf_in, din, 0, "buf_in"), (buf_out, dout, 1, "buf_out")) if t is not None and dt is not None]
+    for device in (False, True):       # every buffer's type and size first, then the devices
+        for t, dt, which, role in bufs:
+            _check_tensor(t, what, dt, _need_bytes(op, m, n, which), role, device)
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -179,12 +230,14 @@ def _stream(stream):
 
 def map_launch(m, n, op, buf_in=None, buf_out=None, r=0, beta=0, stream=None) -> None:
     """H launch of ``op`` over Delta_n^m on the given (or current) stream."""
+    _check_op_buffers("simplex_map_launch", m, n, op, buf_in, buf_out)
     _check(lib().simplex_map_launch(m, n, r, beta, _op(op), _ptr(buf_in), _ptr(buf_out),
                                     _stream(stream)), "simplex_map_launch")
 
 
 def bb_launch(m, n, op, buf_in=None, buf_out=None, stream=None) -> None:
     """Bounding-box launch of ``op`` over Delta_n^m."""
+    _check_op_buffers("simplex_bb_launch", m, n, op, buf_in, buf_out)
     _check(lib().simplex_bb_launch(m, n, _op(op), _ptr(buf_in), _ptr(buf_out), _stream(stream)),
            "simplex_bb_launch")
 
@@ -229,12 +282,15 @@ def set_tile(m, op, rho, wg_threads=0) -> None:
     _check(lib().simplex_set_tile(m, _op(op), rho, wg_threads), "simplex_set_tile")
 
 
-def _job_array(jobs):
-    """jobs: iterable of (m, op, n, buf_in, buf_out) with tensors or raw pointers."""
+def _job_array(jobs, what="simplex_batch_launch"):
+    """jobs: iterable of (m, op, n, buf_in, buf_out) with tensors or raw
+    pointers (raw pointers are passed as they are; tensors are validated)."""
     def p(x):
         return None if x is None else (x if isinstance(x, int) else x.data_ptr())
     arr = (Job * max(len(jobs), 1))()
     for i, (m, op, n, a, b) in enumerate(jobs):
+        if not isinstance(a, int) and not isinstance(b, int):
+            _check_op_buffers(what, m, n, op, a, b)
         arr[i] = Job(m, _op(op), n, p(a), p(b))
     return arr
 
@@ -260,7 +316,7 @@ def queue_launch_raw(jobs, njobs=None, max_workgroups=0, stream_ptr=None) -> int
 def queue_launch(jobs, max_workgroups=0, stream=None) -> None:
     """One step of every (m, op, n, buf_in, buf_out) job in one persistent
     launch that pulls H-mapped block ranges from a device-side work queue."""
-    arr = _job_array(jobs)
+    arr = _job_array(jobs, "simplex_queue_launch")
     _check(lib().simplex_queue_launch(arr, len(jobs), max_workgroups, _stream(stream)),
            "simplex_queue_launch")
 
@@ -280,8 +336,17 @@ def serve_run_raw(jobs, arena_ptr, arena_bytes, mode, max_inflight=4, keep_outpu
 
 
 def serve_run(jobs, arena, mode, max_inflight=4, keep_outputs=False):
-    """Replay a job stream (see simplex_serve_run); `arena` is a uint8 device tensor."""
-    rc, recs = serve_run_raw(jobs, arena.data_ptr(), arena.numel(), mode, max_inflight, keep_outputs)
+    """Replay a job stream (see simplex_serve_run); `arena` is a contiguous
+    device tensor (its byte size is the memory budget)."""
+    what = "simplex_serve_run"
+    arena_types = ("uint8", "int8", "int32", "uint32", "float32")
+    _check_tensor(arena, what, arena_types, 0, "arena", device=False)
+    for (m, op, n, a, _t) in jobs:
+        if not isinstance(a, int):
+            _check_op_buffers(what, m, n, op, a, None)
+    _check_tensor(arena, what, arena_types, 0, "arena")
+    rc, recs = serve_run_raw(jobs, arena.data_ptr(), arena.numel() * arena.element_size(), mode,
+                             max_inflight, keep_outputs)
     _check(rc, "simplex_serve_run")
     return recs
 
@@ -297,6 +362,7 @@ def autotune_raw(m, n, op, in_ptr, out_ptr, reps=20, cache_path=None, stream_ptr
 
 def autotune(m, n, op, buf_in=None, buf_out=None, reps=20, cache_path=None, stream=None) -> dict:
     """Pick (rho, workgroup size, beta) for H launches of (m, n, op) by timing."""
+    _check_op_buffers("simplex_autotune", m, n, op, buf_in, buf_out)
     r = TuneResult()
     _check(lib().simplex_autotune(m, n, _op(op), _ptr(buf_in), _ptr(buf_out), reps,
                                   None if cache_path is None else cache_path.encode(),
@@ -312,6 +378,8 @@ class Graph:
     """A captured run of `steps` H (or BB) launches (simplex_graph_create)."""
 
     def __init__(self, m, n, op, buf_in=None, buf_out=None, steps=1, r=0, beta=0, use_bb=False):
+        self.handle = None
+        _check_op_buffers("simplex_graph_create", m, n, op, buf_in, buf_out)
         h = ctypes.c_void_p()
         _check(lib().simplex_graph_create(m, n, r, beta, _op(op), 1 if use_bb else 0, _ptr(buf_in),
                                           _ptr(buf_out), steps, ctypes.byref(h)), "simplex_graph_create")
@@ -337,8 +405,9 @@ class QueueGraph(Graph):
     graph (simplex_queue_graph_create); replay with launch(), free with close()."""
 
     def __init__(self, jobs, max_workgroups=0):   # pylint: disable=super-init-not-called
+        self.handle = None
         h = ctypes.c_void_p()
-        arr = _job_array(jobs)
+        arr = _job_array(jobs, "simplex_queue_graph_create")
         _check(lib().simplex_queue_graph_create(arr, len(jobs), max_workgroups, ctypes.byref(h)),
                "simplex_queue_graph_create")
         self.handle = h
@@ -357,11 +426,13 @@ def queue_graph_create_raw(jobs, njobs=None, max_workgroups=0) -> int:
 
 def map_launch_steps(m, n, op, steps, buf_in, buf_out, r=0, beta=0, stream=None) -> None:
     """`steps` generations with the H map (several per pass; see the header)."""
+    _check_op_buffers("simplex_map_launch_steps", m, n, op, buf_in, buf_out)
     _check(lib().simplex_map_launch_steps(m, n, r, beta, _op(op), steps, _ptr(buf_in), _ptr(buf_out),
                                           _stream(stream)), "simplex_map_launch_steps")
 
 
 def bb_launch_steps(m, n, op, steps, buf_in, buf_out, stream=None) -> None:
+    _check_op_buffers("simplex_bb_launch_steps", m, n, op, buf_in, buf_out)
     _check(lib().simplex_bb_launch_steps(m, n, _op(op), steps, _ptr(buf_in), _ptr(buf_out),
                                          _stream(stream)), "simplex_bb_launch_steps")
 
@@ -383,3 +454,17 @@ def set_layout(m, layout) -> None:
     """Native layout of the 3-D H map: LAYOUT_AUTO (default: levels for
     one-job CA3 launches, packed otherwise), LAYOUT_PACKED or LAYOUT_LEVELS."""
     _check(lib().simplex_set_layout(m, layout), "simplex_set_layout")
+
+
+def copy_launch(m, n, buf_in, buf_out, stream=None) -> None:
+    """The simplex-cell copy probe (simplex_copy_launch): uint8 boxes, m = 2, 3."""
+    if isinstance(m, int) and isinstance(n, int) and n >= 0:
+        for device in (False, True):
+            for t, role in ((buf_in, "buf_in"), (buf_out, "buf_out")):
+                _check_tensor(t, "simplex_copy_launch", _U8, (n + 1) ** m, role, device)
+    _check(lib().simplex_copy_launch(m, n, _ptr(buf_in), _ptr(buf_out), _stream(stream)),
+           "simplex_copy_launch")
+
+
+def copy_launch_raw(m, n, in_ptr, out_ptr, stream_ptr=None) -> int:
+    return lib().simplex_copy_launch(m, n, in_ptr, out_ptr, stream_ptr)

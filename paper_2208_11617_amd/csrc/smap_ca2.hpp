@@ -197,9 +197,12 @@ __device__ __forceinline__ void ca2_tile(const Plan &P, const uint8_t *__restric
         const int32_t y = ywave + r + lane_rows;
         const bool yin = (uint32_t)y <= (uint32_t)n;   // 0 <= y <= n
         const uint8_t *rowp = in + (int64_t)(ywave + r) * pitch;   // wave-uniform
+        // rows past r = rows (the halo below the last output row) are
+        // never needed: their loads read the buffer's first bytes instead
+        const bool need = yin && r <= rows;            // r <= rows is wave-uniform
         e = 0u;
-        if (is_edge && yin && xe >= 0 && xe <= n - y) e = ld_u32(rowp + off_e);
-        const bool has = yin && x <= n - y;
+        if (is_edge && need && xe >= 0 && xe <= n - y) e = ld_u32(rowp + off_e);
+        const bool has = need && x <= n - y;
         const uint4 q = *reinterpret_cast<const uint4 *>(has ? rowp + off_c : in);
         c[0] = q.x; c[1] = q.y; c[2] = q.z; c[3] = q.w;
     };

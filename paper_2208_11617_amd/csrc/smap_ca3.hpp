@@ -63,10 +63,11 @@ struct Ca3Walk {
 
 // One B6/S567 step of sub-block `sub` of the rho^3 tile t (workgroup body;
 // every thread of the workgroup must call it: it has barriers).
-template <int RHO, int RY, int RZ, int RL, bool SAFE>
+template <int RHO, int RY, int RZ, int RL, bool SAFE, int PD = 2>
 __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restrict__ in,
                                          uint8_t *__restrict__ out, const int32_t *t, uint32_t sub)
 {
+    static_assert(PD >= 2 && PD <= 4, "prefetch depth");
     using Sh = Ca3Walk<RHO, RY, RZ, RL>;
     constexpr int G = Sh::G, NT = Sh::NT, SUBY = Sh::SUBY;
     constexpr int C = (RHO + 8 + 15) / 16;      // 16-byte chunks per staged row (x0-4 .. x0+rho+4)
@@ -83,6 +84,9 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
     if (x0 + y0 + z0 > n) return;                 // uniform: no cell in this sub-block
     // output planes with a simplex cell: z0 .. z0 + nz - 1 (workgroup-uniform)
     const int32_t nz = min(RZ, n - x0 - y0 - z0 + 1);
+    // last staged plane that an output plane reads: z0 + nz (the halo above),
+    // or n; planes beyond it are never loaded
+    const int32_t zhi = min(n, z0 + nz);
     const int64_t p1 = P.stride[1], p2 = P.stride[2];
     const int64_t total = p2 * p1;
     const int tid = threadIdx.x;
@@ -106,7 +110,7 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
     // issued after a register set known, so the wait before its use is a
     // partial one and the loads of the next planes stay in flight.
     auto load_plane = [&](int32_t z, uint4 (&R)[KQ]) {
-        const bool zin = (uint32_t)z <= (uint32_t)n;   // uniform
+        const bool zin = (uint32_t)z <= (uint32_t)zhi;  // uniform
         if constexpr (SAFE) {
 #pragma unroll
             for (int k = 0; k < KQ; ++k) R[k] = make_uint4(0u, 0u, 0u, 0u);
@@ -134,7 +138,14 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
                 chunk_geom(k, y, xs, off);
                 const bool has = zin && (NCH % NT == 0 || tid + k * NT < NCH) && y >= 0 &&
                                  n - z - y - max(xs, 0) >= 0;
-                R[k] = *reinterpret_cast<const uint4 *>(has ? pl + off : in);
+                uint64_t a = has ? (uint64_t)(pl - in) + off : 0u;
+                // The offset is opaque to the compiler: a plane with no cell
+                // in this sub-block (a uniform offset 0) would otherwise
+                // become a scalar load on a branch of its own, and a path
+                // that issues no vector load turns every later wait for a
+                // load into a full drain of the loads in flight.
+                asm("" : "+v"(a));
+                R[k] = *reinterpret_cast<const uint4 *>(in + a);
             }
         }
     };
@@ -156,7 +167,7 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
                 w[0] = 0u;
             }
             // cells x_s .. x_s + v - 1 of the chunk are in the simplex
-            const int32_t v = ((uint32_t)z > (uint32_t)n || y < 0) ? 0 : n - z - y - xs + 1;
+            const int32_t v = ((uint32_t)z > (uint32_t)zhi || y < 0) ? 0 : n - z - y - xs + 1;
             if (v < 16) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -195,23 +206,23 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
         }
     };
 
-    // Two register sets of chunk loads alternate (the plane loop is unrolled
-    // by two), so a set is consumed two planes after its loads were issued
-    // with no register copy in between: a copy would wait for the loads.
-    uint4 RA[KQ], RB[KQ];
-    load_plane(z0 - 1, RA);
-    commit_plane(z0 - 1, RA, 0);
-    load_plane(z0, RA);
-    load_plane(z0 + 1, RB);
-    __syncthreads();
+    // PD register sets of chunk loads rotate (the plane loop is unrolled by
+    // PD), so a set is consumed PD planes after its loads were issued with no
+    // register copy in between: a copy would wait for the loads.
+    uint4 RS[PD][KQ];
+    load_plane(z0 - 1, RS[0]);
+    commit_plane(z0 - 1, RS[0], 0);
+#pragma unroll
+    for (int u = 0; u < PD; ++u) load_plane(z0 + u, RS[u]);
+    lds_barrier();
 
     uint32_t sp[RL][4] = {}, sc[RL][4] = {}, cp[RL][4] = {};
-    // Staged planes z0-1 .. z0+nz; the walk runs an even number of steps so
-    // that both halves of the unrolled loop always run (a step beyond the
-    // last plane stages zeros or unused cells and stores nothing), and every
-    // step issues its loads: the wait before a register set's use then only
-    // covers that set, not the loads issued after it.
-    const int32_t steps = (nz + 3) & ~1;
+    // Staged planes z0-1 .. z0+nz; the walk runs a multiple of PD steps so
+    // that every part of the unrolled loop always runs (a step beyond the
+    // last plane stages zeros and stores nothing), and every step issues
+    // its loads: the wait before a register set's use then only covers that
+    // set, not the loads issued after it.
+    const int32_t steps = (nz + 2 + PD - 1) / PD * PD;
     // Step i: plane z0-1+i is staged in lds[i & 1] and RX holds plane z0+i.
     auto step = [&](int32_t i, uint4 (&RX)[KQ]) {
         uint32_t sn[RL][4], cn[RL][4];
@@ -246,33 +257,50 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
             }
         }
         commit_plane(z0 + i, RX, (i + 1) & 1);   // staged for step i + 1
-        load_plane(z0 + i + 2, RX);               // consumed at step i + 2
-        __syncthreads();
+        load_plane(z0 + i + PD, RX);              // consumed at step i + PD
+        lds_barrier();
     };
-    for (int32_t i = 0; i < steps; i += 2) {
-        step(i, RA);
-        step(i + 1, RB);
+    for (int32_t i = 0; i < steps; i += PD) {
+#pragma unroll
+        for (int u = 0; u < PD; ++u) step(i + u, RS[u]);
     }
 }
 
-// The CA3 kernel.  H: grid (map grid, SUB), x-adjacent tiles of one
-// sub-block position run together.  BB: grid (kbox, kbox, kbox * SUB).
-template <int RHO, int RY, int RZ, int RL, bool BB, bool SAFE>
+// The CA3 kernel.  BB: grid (kbox, kbox, kbox * SUB).  H, ORD = 0: grid
+// (map grid, SUB); x-adjacent tiles of one sub-block position run together.
+// H, ORD = 1: a 1-D grid in which the SUBY sub-blocks that share a tile and
+// a z range (the y-neighbours, whose halo rows overlap) run one after
+// another on one XCD: hardware workgroup L goes to XCD L mod 8, its slot
+// L / 8 on that XCD is (chunk sequence, y sub-block), and the chunks
+// (tile, z range) are dealt to the XCDs in turn, z range slowest.  The grid
+// is padded to whole rounds of 8 chunks; P.grid_div[0] divides by the
+// map's tile count.
+template <int RHO, int RY, int RZ, int RL, bool BB, bool SAFE, int PD = 2, int ORD = 0>
 __global__ __launch_bounds__((RHO / 16) * (RY / RL)) void k_ca3(const Plan P, const uint8_t *__restrict__ in,
                                                                        uint8_t *__restrict__ out)
 {
-    constexpr int SUB = Ca3Walk<RHO, RY, RZ, RL>::SUB;
+    using Sh = Ca3Walk<RHO, RY, RZ, RL>;
+    constexpr int SUB = Sh::SUB, SUBY = Sh::SUBY;
     int32_t t[4] = {0, 0, 0, 0};
     uint32_t sub;
-    const WgId g = wg_id(P);
     if (BB) {
+        const WgId g = wg_id(P);
         decode_bb(P, g.x, g.y, g.z / SUB, t);
         sub = g.z % SUB;
+    } else if (ORD == 1) {
+        const uint32_t L = blockIdx.x;
+        const uint32_t slot = L >> 3;
+        const uint32_t chunk = (slot / SUBY) * 8u + (L & 7u);
+        const uint32_t zb = divu(chunk, P.grid_div[0]);
+        if (zb >= (uint32_t)Sh::SUBZ) return;        // padding of the last round
+        if (!decode_h<3>(P, chunk - zb * P.total, t)) return;
+        sub = zb * SUBY + slot % SUBY;
     } else {
+        const WgId g = wg_id(P);
         if (!decode_h<3>(P, g.x, t)) return;
         sub = g.y;
     }
-    ca3_tile<RHO, RY, RZ, RL, SAFE>(P, in, out, t, sub);
+    ca3_tile<RHO, RY, RZ, RL, SAFE, PD>(P, in, out, t, sub);
 }
 
 }  // namespace smap

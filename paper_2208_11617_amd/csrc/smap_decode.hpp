@@ -155,6 +155,21 @@ __device__ __forceinline__ WgId wg_id(const Plan &P)
 }
 #endif
 
+#if defined(__HIPCC__)
+// Workgroup barrier that orders LDS only: waits for this wave's LDS
+// operations, then s_barrier, with fences restricted to the local address
+// space.  __syncthreads() also waits for every outstanding global load and
+// store (a workgroup-scope fence covers global memory), which would drain the
+// loads that the tile walks keep in flight across barriers; no kernel here
+// passes global-memory data between the waves of a workgroup.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+#endif
+
 SMAP_HD uint32_t ilog2u(uint32_t v)  // floor(log2 v), v > 0: 31 - clz(v)
 {
     return 31u - (uint32_t)__builtin_clz(v);

@@ -21,6 +21,7 @@
 #include "smap_ca2k.hpp"
 #include "smap_ca3k.hpp"
 #include "smap_ca3.hpp"
+#include "smap_copy.hpp"
 #include "smap_plan.hpp"
 #include "smap_point.hpp"
 #include "smap_serve.hpp"
@@ -261,6 +262,48 @@ int check_buffers(int m, int64_t n, int op, const void *in, const void *out)
         const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
         const uintptr_t len = (uintptr_t)elems;
         if (a < b + len && b < a + len) return kEinval;  // overlapping ping-pong buffers
+    }
+    if (op == OP_ACCUM && in != out) {
+        // in place (in == out) is allowed; any other overlap would race
+        const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+        const uintptr_t len = (uintptr_t)elems * 4u;
+        if (a < b + len && b < a + len) return kEinval;
+    }
+    return kOk;
+}
+
+// The buffers of a batch: no job's output may overlap another job's output
+// or input (inputs may be shared).  Each job's own pair is checked by
+// check_buffers.  Sorts the output intervals, checks neighbours, then
+// looks up each input among the outputs: O(k log k).
+int check_batch_buffers(const simplex_job *jobs, int32_t njobs)
+{
+    struct Iv {
+        uintptr_t a, b;
+        int32_t job;
+    };
+    std::vector<Iv> outs;
+    outs.reserve((size_t)njobs);
+    for (int32_t i = 0; i < njobs; ++i) {
+        int64_t elems = 0;
+        if (!box_elems(jobs[i].m, jobs[i].n, &elems)) return kErange;
+        const uintptr_t o = (uintptr_t)jobs[i].buf_out;
+        outs.push_back({o, o + (uintptr_t)elems, i});
+    }
+    std::sort(outs.begin(), outs.end(), [](const Iv &x, const Iv &y) { return x.a < y.a; });
+    for (size_t k = 1; k < outs.size(); ++k)
+        if (outs[k].a < outs[k - 1].b) return kEinval;    // two outputs overlap
+    // sorted, disjoint outputs have sorted ends: the last output that starts
+    // before an input's end is the only one that can reach into it
+    for (int32_t i = 0; i < njobs; ++i) {
+        int64_t elems = 0;
+        box_elems(jobs[i].m, jobs[i].n, &elems);
+        const uintptr_t a = (uintptr_t)jobs[i].buf_in, b = a + (uintptr_t)elems;
+        auto it = std::lower_bound(outs.begin(), outs.end(), b,
+                                   [](const Iv &x, uintptr_t v) { return x.a < v; });
+        if (it == outs.begin()) continue;
+        --it;
+        if (it->b > a && it->job != i) return kEinval;    // another job writes this input
     }
     return kOk;
 }
@@ -721,6 +764,10 @@ int batch_launch(const simplex_job *jobs, int32_t njobs, void *stream)
             items[(ca2 ? 0 : 2) + (J.n < 15 ? 1 : 0)].push_back(it);
         }
     }
+    {
+        const int rc = check_batch_buffers(jobs, njobs);
+        if (rc != kOk) return rc;
+    }
     std::lock_guard<std::mutex> lk(g_batch_mu);
     BatchRing *R = nullptr;
     int rc = ring_for_device(&R);
@@ -833,7 +880,7 @@ int queue_items(const simplex_job *jobs, int32_t njobs, std::vector<BatchItem> &
             kinds.push_back(small ? (ca2 ? kQueueCa2Small : kQueueCa3Small) : (ca2 ? kQueueCa2 : kQueueCa3));
         }
     }
-    return kOk;
+    return check_batch_buffers(jobs, njobs);
 }
 
 // The device-side table of one queue launch: head counter (zero), unit
@@ -1432,6 +1479,25 @@ int simplex_set_layout(int m, int layout)
     std::lock_guard<std::mutex> lk(g_mu);
     g_layout3 = layout;
     return kOk;
+}
+
+int simplex_copy_launch(int m, int64_t n, const void *buf_in, void *buf_out, void *stream)
+{
+    if ((m != 2 && m != 3) || n < 0 || !buf_in || !buf_out) return kEinval;
+    int64_t elems = 0;
+    if (!box_elems(m, n, &elems)) return kErange;
+    if (n + 1 > 65535 && m == 3) return kErange;                 // grid y is the slab
+    const uintptr_t a = (uintptr_t)buf_in, b = (uintptr_t)buf_out;
+    if (a < b + (uintptr_t)elems && b < a + (uintptr_t)elems) return kEinval;
+    const dim3 grid((uint32_t)((n + kCopyRowsPerWg) / kCopyRowsPerWg), m == 3 ? (uint32_t)(n + 1) : 1u);
+    hipStream_t s = (hipStream_t)stream;
+    const uint8_t *i8 = (const uint8_t *)buf_in;
+    uint8_t *o8 = (uint8_t *)buf_out;
+    if (m == 2)
+        hipLaunchKernelGGL(k_simplex_copy<2>, grid, dim3(256), 0, s, (int32_t)n, (int64_t)(n + 1), i8, o8);
+    else
+        hipLaunchKernelGGL(k_simplex_copy<3>, grid, dim3(256), 0, s, (int32_t)n, (int64_t)(n + 1), i8, o8);
+    return hipGetLastError() == hipSuccess ? kOk : kEhip;
 }
 
 const char *simplex_strerror(int status)

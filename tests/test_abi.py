@@ -237,3 +237,46 @@ def test_launch_steps_argument_errors():
     assert smap.launch_steps_raw(2, 100, "ca3", 4, a, b) == E          # CA3 needs m = 3
     assert smap.launch_steps_raw(2, 100, "ca2", 4, a, a + 100) == E     # overlapping buffers
     assert smap.launch_steps_raw(2, 100, "ca2", 4, 0, b) == E           # NULL input
+
+
+def test_accum_partial_overlap_rejected():
+    """ACCUM may run in place (in == out) but not on buffers that overlap
+    otherwise: lanes would read cells that others have already written."""
+    for launch in (smap.map_launch_raw, smap.bb_launch_raw):
+        args = (0, 0) if launch is smap.map_launch_raw else ()
+        for shift in (4, 8, 100, 10 * 11 * 4 - 4, -4, -400):
+            st = launch(2, 10, *args, smap.OP_ACCUM, FAKE, FAKE + shift, None)
+            assert st == smap.EINVAL, shift
+
+
+def test_batch_cross_job_overlap_rejected():
+    """No job's output may overlap another job's output or input, in either
+    batched launch kind; the check runs before anything is enqueued."""
+    E = smap.EINVAL
+    box = 101 * 101
+    a_in, a_out = 1 << 20, 1 << 22
+    b_in, b_out = 1 << 24, 1 << 26
+    for raw in (smap.batch_launch_raw, smap.queue_launch_raw):
+        # outputs overlap
+        assert raw([(2, "ca2", 100, a_in, a_out), (2, "ca2", 100, b_in, a_out + box - 1)]) == E
+        assert raw([(2, "ca2", 100, a_in, a_out + 7), (3, "ca3", 20, b_in, a_out)]) == E
+        # another job's output reaches into an input
+        assert raw([(2, "ca2", 100, a_in, a_out), (2, "ca2", 100, a_out + box - 1, b_out)]) == E
+        assert raw([(2, "ca2", 100, b_out - 5, a_out), (2, "ca2", 100, b_in, b_out)]) == E
+        # the same job set in the other order
+        assert raw([(2, "ca2", 100, b_in, b_out), (2, "ca2", 100, b_out - 5, a_out)]) == E
+    assert smap.queue_graph_create_raw([(2, "ca2", 100, a_in, a_out),
+                                        (2, "ca2", 100, b_in, a_out + 3)]) == E
+
+
+def test_copy_probe_argument_errors():
+    E = smap.EINVAL
+    raw = smap.copy_launch_raw
+    assert raw(4, 10, FAKE, FAKE + (1 << 20)) == E          # m = 2 or 3 only
+    assert raw(1, 10, FAKE, FAKE + (1 << 20)) == E
+    assert raw(2, -1, FAKE, FAKE + (1 << 20)) == E
+    assert raw(2, 10, None, FAKE) == E
+    assert raw(3, 10, FAKE, None) == E
+    assert raw(2, 10, FAKE, FAKE + 120) == E                # overlap (box = 121 B)
+    assert raw(3, 10, FAKE + 1330, FAKE) == E               # overlap (box = 1331 B)
+    assert raw(3, 1 << 20, FAKE, FAKE + (1 << 40)) == smap.ERANGE

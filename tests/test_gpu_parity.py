@@ -239,6 +239,9 @@ def _sample_rows(m, n, rng, k):
     corner = [(0,) * (m - 1), (n,) + (0,) * (m - 2), (0,) * (m - 2) + (n,)]
     for c in corner:
         rows.add(c)
+    if m == 3:  # rows on both sides of the 256-cell tile faces in y and z
+        faces = [v for v in (0, 255, 256, 511, 512, 767, 768) if v <= n]
+        rows.update((y, z) for y in faces for z in faces if y + z <= n)
     while len(rows) < k:
         v = rng.integers(0, n + 1, size=m - 1)
         if v.sum() <= n:
