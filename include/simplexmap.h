@@ -408,6 +408,26 @@ int simplex_queue_launch(const struct simplex_job *jobs, int32_t njobs, int32_t 
 int simplex_queue_graph_create(const struct simplex_job *jobs, int32_t njobs, int32_t max_workgroups,
                                void **graph);
 
+/*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the persistent
+ * work-queue launch of simplex_queue_launch, with the same jobs, kernel and
+ * results, but its job table (head counter, unit prefix sums, jobs) kept in
+ * a fixed device array inside the library instead of the allocated ring.
+ * No call allocates or frees device or pinned memory; the array (about
+ * 100 KB per device, for at most 256 jobs) and a pageable host staging copy
+ * are taken on the first call on a device and held until the process ends.
+ * The table travels with an asynchronous copy on `stream`, the head counter
+ * starting at zero as part of it (no memset); before rewriting the staging
+ * copy, a call waits on the host for the previous call's copy to finish.
+ * Every call on a device shares that device's array and leaves the last
+ * call's table in it: calls on one device must be ordered (one stream, or
+ * streams the caller synchronises); calls that overlap on the device race.
+ * Errors: those of simplex_queue_launch, and SMAP_ERANGE for njobs > 256.
+ */
+int simplex_queue_launch_static(const struct simplex_job *jobs, int32_t njobs, int32_t max_workgroups,
+                                void *stream);
+
 /* ---- serving loop -------------------------------------------------------
  *
  * A request stream of automaton-step jobs (the continuous-batching serving

@@ -25,7 +25,8 @@ EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_autotune", "simplex_autotune_reset", "simplex_graph_create",
            "simplex_graph_launch", "simplex_graph_destroy", "simplex_map_launch_steps",
            "simplex_bb_launch_steps", "simplex_set_layout", "simplex_queue_launch",
-           "simplex_set_general", "simplex_queue_graph_create", "simplex_copy_launch")
+           "simplex_set_general", "simplex_queue_graph_create", "simplex_copy_launch",
+           "simplex_queue_launch_static")
 
 LAYOUT_AUTO, LAYOUT_PACKED, LAYOUT_LEVELS = -1, 0, 1
 GENERAL_FUSED, GENERAL_STREAMS = 0, 1
@@ -146,6 +147,8 @@ def lib():
     L.simplex_bb_launch_steps.restype = ci
     L.simplex_set_layout.argtypes = [ci, ci]
     L.simplex_set_layout.restype = ci
+    L.simplex_queue_launch_static.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_int32, vp]
+    L.simplex_queue_launch_static.restype = ci
     L.simplex_copy_launch.argtypes = [ci, i64, vp, vp, vp]
     L.simplex_copy_launch.restype = ci
     L.simplex_strerror.argtypes = [ci]
@@ -319,6 +322,21 @@ def queue_launch(jobs, max_workgroups=0, stream=None) -> None:
     arr = _job_array(jobs, "simplex_queue_launch")
     _check(lib().simplex_queue_launch(arr, len(jobs), max_workgroups, _stream(stream)),
            "simplex_queue_launch")
+
+
+def queue_launch_static_raw(jobs, njobs=None, max_workgroups=0, stream_ptr=None) -> int:
+    """Status-returning simplex_queue_launch_static (jobs as for batch_launch)."""
+    arr = _job_array(jobs, "simplex_queue_launch_static")
+    return lib().simplex_queue_launch_static(arr, len(jobs) if njobs is None else njobs, max_workgroups,
+                                             stream_ptr)
+
+
+def queue_launch_static(jobs, max_workgroups=0, stream=None) -> None:
+    """simplex_queue_launch without allocation: the job table lives in a
+    fixed device array of the library (at most 256 jobs)."""
+    arr = _job_array(jobs, "simplex_queue_launch_static")
+    _check(lib().simplex_queue_launch_static(arr, len(jobs), max_workgroups, _stream(stream)),
+           "simplex_queue_launch_static")
 
 
 def serve_run_raw(jobs, arena_ptr, arena_bytes, mode, max_inflight=4, keep_outputs=False):

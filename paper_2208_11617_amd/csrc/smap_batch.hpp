@@ -150,9 +150,9 @@ __global__ __launch_bounds__(kQueueThreads) void k_queue(uint32_t *__restrict__ 
     __shared__ uint32_t claim;
     for (;;) {
         if (threadIdx.x == 0) claim = atomicAdd(head, 1u);
-        __syncthreads();
+        lds_barrier();
         const uint32_t u = __builtin_amdgcn_readfirstlane(claim);
-        __syncthreads();   // every wave has read `claim` before the next claim overwrites it
+        lds_barrier();     // every wave has read `claim` before the next claim overwrites it
         if (u >= total) return;
         const uint32_t j = batch_find(start, njobs, u);
         const uint32_t local = u - start[j];

@@ -933,6 +933,87 @@ int queue_launch(const simplex_job *jobs, int32_t njobs, int32_t max_wg, void *s
     return kOk;
 }
 
+// ---- persistent launch without allocation ---------------------------------
+
+// The job table of simplex_queue_launch_static lives in this file-scope
+// device array (one copy per device, held until the process ends): the head
+// counter, the unit prefix sums and the jobs, laid out as queue_table does.
+constexpr int32_t kStaticMaxJobs = 256;
+constexpr size_t kStaticBytes = 256 + ((sizeof(uint32_t) * (kStaticMaxJobs + 1) + 255) / 256) * 256 +
+                                ((sizeof(QueueJob) * kStaticMaxJobs + 255) / 256) * 256;
+__device__ __align__(256) uint8_t scratch[kStaticBytes];
+
+// Per device: the device address of `scratch` (from hipGetSymbolAddress;
+// the array's name is not a device address in host code), a host staging
+// copy of the table (pageable; the copy reads it), and an event recorded
+// after the last copy, so the staging bytes are rewritten only after the
+// previous copy has read them.
+struct StaticTable {
+    uint8_t *dev = nullptr;
+    std::vector<uint8_t> stage;
+    hipEvent_t copied = nullptr;
+    bool pending = false;
+};
+std::mutex g_static_mu;
+std::map<int, StaticTable> g_static;
+
+int static_table_for_device(StaticTable **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kEhip;
+    StaticTable &T = g_static[dev];
+    if (!T.dev) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return kEhip;
+        if (!T.copied && hipEventCreateWithFlags(&T.copied, hipEventDisableTiming) != hipSuccess) return kEhip;
+        T.stage.assign(kStaticBytes, 0);
+        T.dev = static_cast<uint8_t *>(p);
+    }
+    *out = &T;
+    return kOk;
+}
+
+int queue_launch_static(const simplex_job *jobs, int32_t njobs, int32_t max_wg, void *stream)
+{
+    if (njobs < 0 || (njobs > 0 && !jobs) || max_wg < 0) return kEinval;
+    if (njobs > kStaticMaxJobs) return kErange;
+    if (njobs == 0) return kOk;
+    std::vector<BatchItem> items;
+    std::vector<uint32_t> kinds;
+    int rc = queue_items(jobs, njobs, items, kinds);
+    if (rc != kOk) return rc;
+    std::vector<uint8_t> h;
+    size_t start_off = 0, jobs_off = 0;
+    uint64_t units = 0;
+    const size_t bytes = queue_table(items.data(), kinds.data(), njobs, h, &start_off, &jobs_off, &units);
+    if (bytes > kStaticBytes) return kErange;
+    if (units == 0) return kOk;
+    if (units > kMaxWorkgroups) return kErange;
+    uint32_t grid = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        rc = queue_grid_for_device(&grid);
+    }
+    if (rc != kOk) return rc;
+    if (max_wg > 0) grid = std::min(grid, (uint32_t)max_wg);
+    grid = (uint32_t)std::min<uint64_t>(grid, units);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    StaticTable *T = nullptr;
+    rc = static_table_for_device(&T);
+    if (rc != kOk) return rc;
+    // the previous copy out of the staging bytes has finished before they change
+    if (T->pending && hipEventSynchronize(T->copied) != hipSuccess) return kEhip;
+    std::memcpy(T->stage.data(), h.data(), bytes);      // head counter included: starts at zero
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(T->dev, T->stage.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess) return kEhip;
+    if (hipEventRecord(T->copied, s) != hipSuccess) return kEhip;
+    T->pending = true;
+    hipLaunchKernelGGL(k_queue, dim3(grid), dim3(kQueueThreads), 0, s, reinterpret_cast<uint32_t *>(T->dev),
+                       reinterpret_cast<const uint32_t *>(T->dev + start_off),
+                       reinterpret_cast<const QueueJob *>(T->dev + jobs_off), (uint32_t)njobs, (uint32_t)units);
+    return hipGetLastError() == hipSuccess ? kOk : kEhip;
+}
+
 // ---- autotuning -----------------------------------------------------------
 
 // The compiled (rho, threads) choices of (m, op class).
@@ -1367,6 +1448,12 @@ int simplex_batch_launch(const struct simplex_job *jobs, int32_t njobs, void *st
 int simplex_queue_launch(const struct simplex_job *jobs, int32_t njobs, int32_t max_workgroups, void *stream)
 {
     return queue_launch(jobs, njobs, max_workgroups, stream);
+}
+
+int simplex_queue_launch_static(const struct simplex_job *jobs, int32_t njobs, int32_t max_workgroups,
+                                void *stream)
+{
+    return queue_launch_static(jobs, njobs, max_workgroups, stream);
 }
 
 int simplex_serve_run(const struct simplex_serve_job *jobs, int32_t njobs, void *arena,
