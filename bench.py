@@ -130,25 +130,27 @@ def time_launches(fn, steps, warmup, stream, stats=None, batches=10, sem_target=
 
 
 def tile_sweep(m, op, fn_for, steps, warmup, stream):
-    """H and BB at every compiled (rho, workgroup size) of the op class, each
-    pair with the same tile (same-shape); returns the list of timings."""
+    """H and BB at every compiled (rho, workgroup size, tiles per workgroup)
+    of the op class, each pair with the same shape (same-shape); returns the
+    list of timings."""
     from paper_2208_11617_amd import binding as smap
     rows = []
-    smap.autotune_reset()   # H launches follow set_tile only without a tuned choice
+    smap.autotune_reset()   # H launches follow set_shape only without a tuned choice
     try:
         for rho in (4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096):
             for wg in (64, 128, 256, 512):
-                try:
-                    smap.set_tile(m, op, rho, wg)
-                except smap.SimplexMapError:
-                    continue   # not compiled for this class
-                row = {"rho": rho, "wg_threads": wg}
-                for name, launch in (("h", smap.map_launch), ("bb", smap.bb_launch)):
+                for grp in (1, 2, 4, 8, 16):
                     try:
-                        row[f"{name}_ms"] = time_launches(fn_for(launch), steps, warmup, stream)
+                        smap.set_shape(m, op, rho, wg, grp)
                     except smap.SimplexMapError:
-                        row[f"{name}_ms"] = None   # beyond the grid limits
-                rows.append(row)
+                        continue   # not compiled for this class
+                    row = {"rho": rho, "wg_threads": wg, "tiles_per_wg": grp}
+                    for name, launch in (("h", smap.map_launch), ("bb", smap.bb_launch)):
+                        try:
+                            row[f"{name}_ms"] = time_launches(fn_for(launch), steps, warmup, stream)
+                        except smap.SimplexMapError:
+                            row[f"{name}_ms"] = None   # beyond the grid limits
+                    rows.append(row)
     finally:
         smap.set_tile(m, op, 0)
     return rows
@@ -158,8 +160,10 @@ def best_vs_best(rows):
     """The fastest H and the fastest BB of a tile sweep, each tuned on its own."""
     h = min((r for r in rows if r["h_ms"] is not None), key=lambda r: r["h_ms"])
     b = min((r for r in rows if r["bb_ms"] is not None), key=lambda r: r["bb_ms"])
-    return {"h": {"rho": h["rho"], "wg_threads": h["wg_threads"], "ms_per_step": h["h_ms"]},
-            "bb": {"rho": b["rho"], "wg_threads": b["wg_threads"], "ms_per_step": b["bb_ms"]},
+    return {"h": {"rho": h["rho"], "wg_threads": h["wg_threads"], "tiles_per_wg": h["tiles_per_wg"],
+                  "ms_per_step": h["h_ms"]},
+            "bb": {"rho": b["rho"], "wg_threads": b["wg_threads"], "tiles_per_wg": b["tiles_per_wg"],
+                   "ms_per_step": b["bb_ms"]},
             "h_vs_bb_speedup": b["bb_ms"] / h["h_ms"], "same_shape": rows}
 
 
@@ -412,6 +416,8 @@ def main():
                     help="H launches: all pieces in one launch, or one launch per piece on streams of their own")
     ap.add_argument("--layout3", default="auto", choices=["auto", "packed", "levels"],
                     help="native layout of the 3-D H map")
+    ap.add_argument("--shape", default=None,
+                    help="rho,threads,tiles_per_wg for H and BB (simplex_set_shape); default: the library's")
     ap.add_argument("--gens", type=int, default=0,
                     help="automata: time simplex_map_launch_steps advancing this many generations per call")
     ap.add_argument("--best-vs-best", action="store_true",
@@ -448,6 +454,9 @@ def main():
     useful = smap.count(m, n)
     if m == 3:
         set_layout3(smap, args.layout3)
+    if args.shape:
+        rho, wg, grp = (int(v) for v in args.shape.split(","))
+        smap.set_shape(m, op, rho, wg, grp)
     smap.set_general(smap.GENERAL_STREAMS if args.general == "streams" else smap.GENERAL_FUSED)
 
     log(f"generating {args.workload}: m={m} n={n} op={op}")
@@ -574,7 +583,9 @@ def main():
                    "rho": info_h["rho"] if args.gens == 0 else (256 if m == 2 else 64),
                    "beta": info_h["beta"], "autotuned": tuned, "graph_launches": args.graph or None,
                    "generations_per_call": gens, "layout3": args.layout3 if m == 3 else None,
-                   "general": args.general},
+                   "general": args.general,
+                   "wg_threads": None if args.gens else info_h["wg_threads"],
+                   "tiles_per_wg": None if args.gens else info_h["tiles_per_wg"]},
         "hbm_gbs_algorithmic": achieved,
         "bb": None if bb_ms is None else {
             "ms_per_step": bb_ms, "value": useful * gens / (bb_ms * 1e-3),

@@ -100,6 +100,10 @@ struct simplex_plan_info {
     uint64_t launched_wgs;    /* workgroups: launched_tiles * wgs_per_tile       */
     uint64_t native_wgs;      /* tiles in the native piece (H only)              */
     uint64_t full_tiles;      /* tiles lying entirely inside the simplex         */
+    int32_t  tiles_per_wg;    /* map units per workgroup (pointwise ops), >= 1;
+                                 above 1, launched_wgs is ceil(launched_tiles /
+                                 tiles_per_wg) for H, ceil(kbox / tiles_per_wg)
+                                 workgroups per row of the tile grid for BB   */
 };
 
 /*
@@ -157,8 +161,9 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
  * the compiled combinations are accepted (others: SMAP_EUNSUPPORTED):
  *   MAP/ACCUM/HITS/HASH  m=2: rho 32 (256 threads), 16 (64), 64 (256), 128 (256)
  *                        m=3: rho 16 (256), 8 (128), 32 (256)
- *                        m=4: rho 8 (256), 4 (64), 16 (256)
- *                        (the first listed rho of each m is the default)
+ *                        m=4: rho 8 (256; two tiles per workgroup), 4 (64), 16 (256)
+ *                        (the first listed rho of each m is the default; more
+ *                        shapes through simplex_set_shape)
  *   CA2 (m=2): rho 1024 (64 threads; 128 or 256), 512 (512), 256 (256),
  *              128 (128), 2048 (128 or 256), 4096 (256).  From 2048 on
  *              the waves of a workgroup stand side by side along x, each
@@ -172,6 +177,27 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
  * of the listed sizes.
  */
 int simplex_set_tile(int m, int op, int rho, int wg_threads);
+
+/*
+ * simplex_set_tile with the number of tiles per workgroup as well, for the
+ * pointwise ops (MAP, ACCUM, HITS, HASH): a workgroup then takes
+ * tiles_per_wg consecutive map units -- which the H map places
+ * x_1-adjacent wherever a cube of the map runs along x_1 -- with its lanes
+ * side by side across their rows, so one store of a wave covers
+ * tiles_per_wg tile rows of contiguous memory (for BB: tiles_per_wg
+ * x_1-adjacent box tiles).  Compiled shapes beyond simplex_set_tile's:
+ *   m=4: rho 8 (256 threads: 2, 4 or 8 tiles; 128 threads: 2 or 4 tiles;
+ *        64 threads: 1, 2 or 4 tiles), rho 4 (256 threads: 8 or 16 tiles)
+ *   m=3: rho 16 (256 threads: 2 tiles; 64 threads: 1 or 2 tiles),
+ *        rho 8 (256 threads: 4 tiles)
+ *   m=2: rho 32 (64 threads: 1 or 2 tiles)
+ * tiles_per_wg = 0 takes the first listed grouping of (rho, wg_threads)
+ * (simplex_set_tile's choice; 1 for the shapes simplex_set_tile lists), 1
+ * asks for one tile per workgroup.  The automata accept 0 or 1 only.
+ * Returns SMAP_EUNSUPPORTED for a combination that is not compiled,
+ * SMAP_EINVAL for a negative wg_threads or tiles_per_wg.
+ */
+int simplex_set_shape(int m, int op, int rho, int wg_threads, int tiles_per_wg);
 
 /*
  * Layout of the native part of the 3-D H map for later launches of this
@@ -224,11 +250,12 @@ struct simplex_tune_result {
     int32_t wg_threads;
     int32_t beta;
     float us;             /* mean duration of one H launch, microseconds */
+    int32_t tiles_per_wg; /* map units per workgroup of the chosen shape */
 };
 
 /*
- * Times every compiled (rho, workgroup size) of (m, op) -- and beta 3 and 4
- * for m = 4 -- with `reps` H launches each (after 2 warm-up launches) on
+ * Times every compiled shape (rho, workgroup size, tiles per workgroup) of
+ * (m, op) -- and beta 3 and 4 for m = 4 -- with `reps` H launches each (after 2 warm-up launches) on
  * `stream`, picks the fastest, and installs it for later H launches of this
  * (m, n, op class) in this process (the tile of simplex_set_tile still
  * applies to other n, and to BB).  A later simplex_map_launch with beta = 0
@@ -238,8 +265,10 @@ struct simplex_tune_result {
  * Synchronises `stream`.
  *
  * cache_path (may be NULL): a text file of earlier results, one line per
- * (device, m, n, op).  If it holds this key, that result is installed and
- * returned with no timing; otherwise the new result is appended.
+ * (device, m, n, op) ("smap-tune-v2 <device> m n op rho threads
+ * tiles_per_wg beta us"; lines of other formats are ignored).  If it holds
+ * this key, that result is installed and returned with no timing;
+ * otherwise the new result is appended.
  *
  * Errors as for simplex_map_launch; reps < 1 gives SMAP_EINVAL; a cache
  * file that cannot be written gives SMAP_EINVAL after installing the result.

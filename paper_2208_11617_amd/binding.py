@@ -26,7 +26,7 @@ EXPORTS = ("simplex_map_launch", "simplex_bb_launch", "simplex_count",
            "simplex_graph_launch", "simplex_graph_destroy", "simplex_map_launch_steps",
            "simplex_bb_launch_steps", "simplex_set_layout", "simplex_queue_launch",
            "simplex_set_general", "simplex_queue_graph_create", "simplex_copy_launch",
-           "simplex_queue_launch_static")
+           "simplex_queue_launch_static", "simplex_set_shape")
 
 LAYOUT_AUTO, LAYOUT_PACKED, LAYOUT_LEVELS = -1, 0, 1
 GENERAL_FUSED, GENERAL_STREAMS = 0, 1
@@ -60,6 +60,7 @@ class PlanInfo(ctypes.Structure):
         ("launched_wgs", ctypes.c_uint64),
         ("native_wgs", ctypes.c_uint64),
         ("full_tiles", ctypes.c_uint64),
+        ("tiles_per_wg", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -89,7 +90,7 @@ class ServeRecord(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     """struct simplex_tune_result"""
     _fields_ = [("rho", ctypes.c_int32), ("wg_threads", ctypes.c_int32), ("beta", ctypes.c_int32),
-                ("us", ctypes.c_float)]
+                ("us", ctypes.c_float), ("tiles_per_wg", ctypes.c_int32)]
 
 
 _lib = None
@@ -118,6 +119,8 @@ def lib():
     L.simplex_plan_tiles.restype = ci
     L.simplex_set_tile.argtypes = [ci, ci, ci, ci]
     L.simplex_set_tile.restype = ci
+    L.simplex_set_shape.argtypes = [ci, ci, ci, ci, ci]
+    L.simplex_set_shape.restype = ci
     L.simplex_batch_launch.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, vp]
     L.simplex_batch_launch.restype = ci
     L.simplex_queue_graph_create.argtypes = [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_int32,
@@ -283,6 +286,11 @@ def plan_tiles(m, n, op, use_bb=False, r=0, beta=0):
 
 def set_tile(m, op, rho, wg_threads=0) -> None:
     _check(lib().simplex_set_tile(m, _op(op), rho, wg_threads), "simplex_set_tile")
+
+
+def set_shape(m, op, rho, wg_threads=0, tiles_per_wg=0) -> None:
+    """simplex_set_shape: tile side, threads and tiles per workgroup."""
+    _check(lib().simplex_set_shape(m, _op(op), rho, wg_threads, tiles_per_wg), "simplex_set_shape")
 
 
 def _job_array(jobs, what="simplex_batch_launch"):

@@ -33,7 +33,8 @@ namespace {
 struct TileCfg {
     int rho;
     int wg;
-    int sub;  // workgroups per tile (CA2 splits a tile into row sub-blocks)
+    int sub;      // workgroups per tile (CA2 splits a tile into row sub-blocks)
+    int grp = 1;  // tiles per workgroup (pointwise ops: x_1-adjacent map units)
 };
 
 // CA2 shapes: (rho, threads) -> waves W, rows per wave R, sub-blocks per tile.
@@ -47,14 +48,24 @@ constexpr Ca2Shape kCa2Shapes[] = {
     {2048, 128, 2, 16, 128}, {2048, 256, 4, 16, 64}, {4096, 256, 4, 16, 256},
 };
 
-// Pointwise shapes: (m, rho) -> threads, sub-blocks per tile.
+// Pointwise shapes: (m, rho) -> threads, sub-blocks per tile, tiles per
+// workgroup.  The first listed shape of an m is its default; the first
+// listed grouping of an (m, rho, threads) is the one simplex_set_tile picks.
 struct PointShape {
-    int m, rho, wg, sub;
+    int m, rho, wg, sub, grp;
 };
 constexpr PointShape kPointShapes[] = {
-    {2, 32, 256, 1}, {2, 16, 64, 1}, {2, 64, 256, 1}, {2, 128, 256, 2},
-    {3, 16, 256, 1}, {3, 8, 128, 1}, {3, 32, 256, 4},
-    {4, 8, 256, 1},  {4, 4, 64, 1},  {4, 16, 256, 16},
+    {2, 32, 256, 1, 1}, {2, 16, 64, 1, 1}, {2, 64, 256, 1, 1}, {2, 128, 256, 2, 1},
+    {3, 16, 256, 1, 1}, {3, 8, 128, 1, 1}, {3, 32, 256, 4, 1},
+    // m = 4: two x_1-adjacent rho = 8 tiles per workgroup (64-byte row runs)
+    {4, 8, 256, 1, 2},  {4, 4, 64, 1, 1},  {4, 16, 256, 16, 1},
+    // several x_1-adjacent tiles per workgroup, or one
+    {4, 8, 256, 1, 1},  {4, 8, 256, 1, 4}, {4, 8, 128, 1, 4}, {4, 8, 256, 1, 8},
+    {4, 4, 256, 1, 8},  {4, 4, 256, 1, 16},
+    {3, 16, 256, 1, 2}, {3, 8, 256, 1, 4},
+    // one wave per workgroup: the scalar decode runs once per workgroup
+    {4, 8, 64, 1, 1},   {4, 8, 64, 1, 2},  {4, 8, 64, 1, 4},  {4, 8, 128, 1, 2},
+    {3, 16, 64, 1, 1},  {3, 16, 64, 1, 2}, {2, 32, 64, 1, 1}, {2, 32, 64, 1, 2},
 };
 
 // CA3 shapes: (rho, threads) -> rows RY (y), planes RZ (z), rows per lane RL.
@@ -90,23 +101,29 @@ TileCfg default_tile(int m, int64_t n, int cls)
         return {128, 256, (128 / 64) * (128 / ca3_rz(128))};
     }
     for (const PointShape &c : kPointShapes)  // the first listed shape of an m is its default
-        if (c.m == m) return {c.rho, c.wg, c.sub};
+        if (c.m == m) return {c.rho, c.wg, c.sub, c.grp};
     return {0, 0, 1};
 }
 
-bool tile_supported(int m, int cls, int rho, int *wg, int *sub)
+// The compiled shape of (m, class, rho, threads, tiles per workgroup);
+// *wg = 0 or *grp = 0 take the first listed match.  The automata have no
+// grouping (*grp must be 0 or 1).
+bool tile_supported(int m, int cls, int rho, int *wg, int *sub, int *grp)
 {
     *sub = 1;
     if (cls == 0) {
         for (const PointShape &c : kPointShapes) {
-            if (c.m == m && c.rho == rho && (*wg == 0 || *wg == c.wg)) {
+            if (c.m == m && c.rho == rho && (*wg == 0 || *wg == c.wg) && (*grp == 0 || *grp == c.grp)) {
                 *wg = c.wg;
                 *sub = c.sub;
+                *grp = c.grp;
                 return true;
             }
         }
         return false;
     }
+    if (*grp > 1) return false;
+    *grp = 1;
     if (cls == 1) {  // the first listed shape of a rho is its default
         for (const Ca2Shape &c : kCa2Shapes) {
             if (c.rho == rho && (*wg == 0 || *wg == c.wg)) {
@@ -315,13 +332,23 @@ void launch_point(const Plan &P, dim3 grid, const void *in, void *out, hipStream
                        (const uint32_t *)in, (uint32_t *)out);
 }
 
+template <int M, int RHO, int NT, int OP, bool BB, int U>
+void launch_point_grp(const Plan &P, dim3 grid, const void *in, void *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_point_grp<M, RHO, NT, OP, BB, U>), grid, dim3(NT), 0, s, P,
+                       (const uint32_t *)in, (uint32_t *)out);
+}
+
 template <int OP, bool BB>
-int dispatch_point_shape(int m, int rho, const Plan &P, dim3 grid, const void *in, void *out,
+int dispatch_point_shape(int m, const TileCfg &tc, const Plan &P, dim3 grid, const void *in, void *out,
                          hipStream_t s)
 {
-    switch (m * 1000 + rho) {
+    const int64_t key = ((int64_t)m * 10000 + tc.rho) * 100000 + (int64_t)tc.wg * 100 + tc.grp;
+    switch (key) {
 #define SMAP_PT(M, RHO, NT, SUB) \
-    case M * 1000 + RHO: launch_point<M, RHO, NT, SUB, OP, BB>(P, grid, in, out, s); return kOk;
+    case ((int64_t)M * 10000 + RHO) * 100000 + NT * 100 + 1: launch_point<M, RHO, NT, SUB, OP, BB>(P, grid, in, out, s); return kOk;
+#define SMAP_PTG(M, RHO, NT, U) \
+    case ((int64_t)M * 10000 + RHO) * 100000 + NT * 100 + U: launch_point_grp<M, RHO, NT, OP, BB, U>(P, grid, in, out, s); return kOk;
     SMAP_PT(2, 32, 256, 1)
     SMAP_PT(2, 16, 64, 1)
     SMAP_PT(2, 64, 256, 1)
@@ -332,23 +359,40 @@ int dispatch_point_shape(int m, int rho, const Plan &P, dim3 grid, const void *i
     SMAP_PT(4, 8, 256, 1)
     SMAP_PT(4, 4, 64, 1)
     SMAP_PT(4, 16, 256, 16)
+    SMAP_PT(4, 8, 64, 1)
+    SMAP_PT(3, 16, 64, 1)
+    SMAP_PT(2, 32, 64, 1)
+    SMAP_PTG(4, 8, 64, 2)
+    SMAP_PTG(4, 8, 64, 4)
+    SMAP_PTG(4, 8, 128, 2)
+    SMAP_PTG(3, 16, 64, 2)
+    SMAP_PTG(2, 32, 64, 2)
+    SMAP_PTG(4, 8, 256, 4)
+    SMAP_PTG(4, 8, 128, 4)
+    SMAP_PTG(4, 8, 256, 2)
+    SMAP_PTG(4, 8, 256, 8)
+    SMAP_PTG(4, 4, 256, 8)
+    SMAP_PTG(4, 4, 256, 16)
+    SMAP_PTG(3, 16, 256, 2)
+    SMAP_PTG(3, 8, 256, 4)
 #undef SMAP_PT
+#undef SMAP_PTG
     }
     return kEunsupported;
 }
 
 template <bool BB>
-int dispatch_point(int op, int m, int rho, const Plan &P, dim3 grid, const void *in, void *out,
+int dispatch_point(int op, int m, const TileCfg &tc, const Plan &P, dim3 grid, const void *in, void *out,
                    hipStream_t s)
 {
     switch (op) {
-    case OP_MAP: return dispatch_point_shape<OP_MAP, BB>(m, rho, P, grid, in, out, s);
-    case OP_ACCUM: return dispatch_point_shape<OP_ACCUM, BB>(m, rho, P, grid, in, out, s);
-    case OP_HITS: return dispatch_point_shape<OP_HITS, BB>(m, rho, P, grid, in, out, s);
-    case OP_HASH: return dispatch_point_shape<OP_HASH, BB>(m, rho, P, grid, in, out, s);
+    case OP_MAP: return dispatch_point_shape<OP_MAP, BB>(m, tc, P, grid, in, out, s);
+    case OP_ACCUM: return dispatch_point_shape<OP_ACCUM, BB>(m, tc, P, grid, in, out, s);
+    case OP_HITS: return dispatch_point_shape<OP_HITS, BB>(m, tc, P, grid, in, out, s);
+    case OP_HASH: return dispatch_point_shape<OP_HASH, BB>(m, tc, P, grid, in, out, s);
     case OP_EDM:
-        if (m != 2) return kEinval;
-        switch (rho) {
+        if (m != 2 || tc.grp != 1) return kEinval;
+        switch (tc.rho) {
         case 32: launch_point<2, 32, 256, 1, OP_EDM, BB>(P, grid, in, out, s); return kOk;
         case 16: launch_point<2, 16, 64, 1, OP_EDM, BB>(P, grid, in, out, s); return kOk;
         case 64: launch_point<2, 64, 256, 1, OP_EDM, BB>(P, grid, in, out, s); return kOk;
@@ -359,6 +403,36 @@ int dispatch_point(int op, int m, int rho, const Plan &P, dim3 grid, const void 
     return kEinval;
 }
 
+// CA3 launch order (H): 0 = grid (map units, sub-blocks), hardware order;
+// 1 = the y-neighbour sub-blocks of a tile and z range one after another on
+// one XCD (k_ca3's ORD = 1 grid).  Prefetch depth: planes of chunk loads in
+// flight per workgroup.
+#ifndef SMAP_CA3_ORD
+#define SMAP_CA3_ORD 0
+#endif
+#ifndef SMAP_CA3_PD
+#define SMAP_CA3_PD 2
+#endif
+template <int RHO, int RY, int RZ, int RL, bool BB>
+void launch_ca3(Plan PL, dim3 grid, const uint8_t *in, uint8_t *out, hipStream_t s)
+{
+    constexpr int ORD = BB ? 0 : SMAP_CA3_ORD;
+    if (ORD == 1) {
+        using Sh = Ca3Walk<RHO, RY, RZ, RL>;
+        const uint64_t chunks = (uint64_t)PL.total * Sh::SUBZ;   // (tile, z range) pairs
+        grid = dim3((uint32_t)((chunks + 7) / 8 * 8 * Sh::SUBY), 1, 1);
+        PL.grid[0] = grid.x;
+        PL.grid[1] = PL.grid[2] = 1;
+        PL.nwg = grid.x;
+        PL.grid_div[0] = make_divu(PL.total);
+        PL.remap = 0;
+    }
+    if (PL.n < 15)
+        hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, true, SMAP_CA3_PD, ORD>), grid, dim3(Ca3Walk<RHO, RY, RZ, RL>::NT), 0, s, PL, in, out);
+    else
+        hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, false, SMAP_CA3_PD, ORD>), grid, dim3(Ca3Walk<RHO, RY, RZ, RL>::NT), 0, s, PL, in, out);
+}
+
 template <bool BB>
 int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, void *out,
              hipStream_t s)
@@ -366,14 +440,16 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
     dim3 grid;
     const Plan &P = P0;  // grid and plan checks
     const uint32_t sub = (uint32_t)tc.sub;
+    const uint32_t grp = (uint32_t)tc.grp;   // > 1 only for the pointwise ops (then sub = 1)
     if (BB) {
         const uint32_t kb = (uint32_t)P.kbox;
+        const uint32_t kx = (kb + grp - 1) / grp;
         if (op == OP_CA2)
             grid = dim3(kb, kb * sub, 1);
         else
-            grid = (m == 2) ? dim3(kb, kb, sub) : (m == 3 ? dim3(kb, kb, kb * sub) : dim3(kb, kb, kb * kb * sub));
+            grid = (m == 2) ? dim3(kx, kb, sub) : (m == 3 ? dim3(kx, kb, kb * sub) : dim3(kx, kb, kb * kb * sub));
     } else {
-        grid = (op == OP_CA3) ? dim3(P.total, sub, 1) : dim3(P.total * sub, 1, 1);
+        grid = (op == OP_CA3) ? dim3(P.total, sub, 1) : dim3((P.total + grp - 1) / grp * sub, 1, 1);
     }
     Plan PL = P0;  // the kernels renumber workgroups over this grid
     PL.grid[0] = grid.x;
@@ -390,7 +466,10 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
     // faster in the hardware order: MAP (no memory traffic to share) and the
     // 3-D automaton (its sub-major order already spreads the concurrent
     // workgroups over the buffer).
-    PL.remap = (BB || op == OP_CA3 || op == OP_MAP) ? 0u : 1u;
+#ifndef SMAP_CA3_REMAP
+#define SMAP_CA3_REMAP 0
+#endif
+    PL.remap = (BB || (op == OP_CA3 && !SMAP_CA3_REMAP) || op == OP_MAP) ? 0u : 1u;
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
         uint8_t *o8 = (uint8_t *)out;
@@ -426,10 +505,8 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
         switch (tc.rho * 10000 + tc.wg) {
 #define SMAP_CA3(RHO, WG, RY, RZ, RL)                                                             \
         case RHO * 10000 + WG:                                                                    \
-            if (P.n < 15)                                                                         \
-                hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, true>), grid, dim3(WG), 0, s, PL, i8, o8); \
-            else                                                                                  \
-                hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, false>), grid, dim3(WG), 0, s, PL, i8, o8); \
+            static_assert(Ca3Walk<RHO, RY, RZ, RL>::NT == WG, "CA3 shape");                      \
+            launch_ca3<RHO, RY, RZ, RL, BB>(PL, grid, i8, o8, s);                                 \
             return kOk;
         SMAP_CA3(128, 256, 64, ca3_rz(128), 2)
         SMAP_CA3(128, 128, 32, ca3_rz(128), 2)
@@ -442,7 +519,7 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
         }
         return kEunsupported;
     }
-    return dispatch_point<BB>(op, m, tc.rho, PL, grid, in, out, s);
+    return dispatch_point<BB>(op, m, tc, PL, grid, in, out, s);
 }
 
 // The pieces of an H launch as concurrent launches: one stream per piece
@@ -1022,7 +1099,7 @@ std::vector<TileCfg> tile_candidates(int m, int cls)
     std::vector<TileCfg> v;
     if (cls == 0) {
         for (const PointShape &c : kPointShapes)
-            if (c.m == m) v.push_back({c.rho, c.wg, c.sub});
+            if (c.m == m) v.push_back({c.rho, c.wg, c.sub, c.grp});
     } else if (cls == 1) {
         for (const Ca2Shape &c : kCa2Shapes) v.push_back({c.rho, c.wg, c.sub});
     } else {
@@ -1051,12 +1128,13 @@ bool cache_lookup(const char *path, const char *dev, int m, int64_t n, int op, s
     char line[256], d[96];
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
-        int mm, oo, rho, wg, beta;
+        int mm, oo, rho, wg, beta, grp;
         long long nn;
         float us;
-        if (std::sscanf(line, "smap-tune-v1 %95s %d %lld %d %d %d %d %f", d, &mm, &nn, &oo, &rho, &wg, &beta, &us) == 8 &&
+        if (std::sscanf(line, "smap-tune-v2 %95s %d %lld %d %d %d %d %d %f", d, &mm, &nn, &oo, &rho, &wg, &grp, &beta,
+                        &us) == 9 &&
             std::strcmp(d, dev) == 0 && mm == m && nn == n && oo == op) {
-            *r = simplex_tune_result{rho, wg, beta, us};
+            *r = simplex_tune_result{rho, wg, beta, us, grp};
             found = true;  // the last matching line wins
         }
     }
@@ -1079,10 +1157,10 @@ int autotune(int m, int64_t n, int op, const void *in, void *out, int32_t reps, 
     if (!device_key(dev, sizeof dev)) return kEhip;
     simplex_tune_result r{};
     if (cache_path && cache_lookup(cache_path, dev, m, n, op, &r)) {
-        int wg = r.wg_threads, sub = 1;
-        if (tile_supported(m, cls, r.rho, &wg, &sub)) {
+        int wg = r.wg_threads, sub = 1, grp = r.tiles_per_wg;
+        if (tile_supported(m, cls, r.rho, &wg, &sub, &grp)) {
             std::lock_guard<std::mutex> lk(g_mu);
-            g_tuned[key] = Tuned{{r.rho, wg, sub}, r.beta};
+            g_tuned[key] = Tuned{{r.rho, wg, sub, grp}, r.beta};
             *best = r;
             return kOk;
         }
@@ -1095,7 +1173,7 @@ int autotune(int m, int64_t n, int op, const void *in, void *out, int32_t reps, 
         return kEhip;
     }
     const std::vector<int> betas = m == 4 ? std::vector<int>{3, 4} : std::vector<int>{2};
-    simplex_tune_result top{0, 0, 0, 0.f};
+    simplex_tune_result top{0, 0, 0, 0.f, 1};
     bool have = false;
     rc = kOk;
     for (const TileCfg &t : tile_candidates(m, cls)) {
@@ -1115,7 +1193,7 @@ int autotune(int m, int64_t n, int op, const void *in, void *out, int32_t reps, 
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = kEhip; break; }
             const float us = ms * 1e3f / (float)reps;
-            if (!have || us < top.us) top = simplex_tune_result{t.rho, t.wg, beta, us};
+            if (!have || us < top.us) top = simplex_tune_result{t.rho, t.wg, beta, us, t.grp};
             have = true;
         }
         if (rc != kOk) break;
@@ -1127,15 +1205,15 @@ int autotune(int m, int64_t n, int op, const void *in, void *out, int32_t reps, 
         g_tuned.erase(key);
         return rc != kOk ? rc : kErange;
     }
-    int wg = top.wg_threads, sub = 1;
-    tile_supported(m, cls, top.rho, &wg, &sub);
-    g_tuned[key] = Tuned{{top.rho, wg, sub}, top.beta};
+    int wg = top.wg_threads, sub = 1, grp = top.tiles_per_wg;
+    tile_supported(m, cls, top.rho, &wg, &sub, &grp);
+    g_tuned[key] = Tuned{{top.rho, wg, sub, grp}, top.beta};
     *best = top;
     if (cache_path) {
         FILE *f = std::fopen(cache_path, "a");
         if (!f) return kEinval;
-        std::fprintf(f, "smap-tune-v1 %s %d %lld %d %d %d %d %.3f\n", dev, m, (long long)n, op, top.rho,
-                     top.wg_threads, top.beta, top.us);
+        std::fprintf(f, "smap-tune-v2 %s %d %lld %d %d %d %d %d %.3f\n", dev, m, (long long)n, op, top.rho,
+                     top.wg_threads, top.tiles_per_wg, top.beta, top.us);
         std::fclose(f);
     }
     return kOk;
@@ -1378,7 +1456,14 @@ int simplex_plan_info(int m, int64_t n, int r, int beta, int op, int use_bb,
     info.useful_tiles = C.useful_tiles;
     info.launched_tiles = C.launched;
     info.wgs_per_tile = tc.sub;
-    info.launched_wgs = C.launched * (uint64_t)tc.sub;
+    info.tiles_per_wg = tc.grp;
+    if (tc.grp > 1) {
+        // H: consecutive map units; BB: rows of the tile grid cut along x_1
+        const uint64_t kb = (uint64_t)P.kbox, g = (uint64_t)tc.grp;
+        info.launched_wgs = use_bb ? (kb + g - 1) / g * (C.launched / kb) : (C.launched + g - 1) / g;
+    } else {
+        info.launched_wgs = C.launched * (uint64_t)tc.sub;
+    }
     info.native_wgs = C.native;
     info.full_tiles = C.full_tiles;
     *out = info;
@@ -1423,21 +1508,26 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb, in
     return kOk;
 }
 
-int simplex_set_tile(int m, int op, int rho, int wg_threads)
+int simplex_set_shape(int m, int op, int rho, int wg_threads, int tiles_per_wg)
 {
     int rc = check_op(m, 0, op);
     if (rc != kOk) return rc;
+    if (wg_threads < 0 || tiles_per_wg < 0) return kEinval;
     const int cls = op_class(op);
     std::lock_guard<std::mutex> lk(g_mu);
     if (rho == 0) {
         g_tiles.erase({m, cls});
         return kOk;
     }
-    int wg = wg_threads, sub = 1;
-    if (!tile_supported(m, cls, rho, &wg, &sub)) return kEunsupported;
-    if (wg_threads != 0 && wg_threads != wg) return kEunsupported;
-    g_tiles[{m, cls}] = TileCfg{rho, wg, sub};
+    int wg = wg_threads, sub = 1, grp = tiles_per_wg;
+    if (!tile_supported(m, cls, rho, &wg, &sub, &grp)) return kEunsupported;
+    g_tiles[{m, cls}] = TileCfg{rho, wg, sub, grp};
     return kOk;
+}
+
+int simplex_set_tile(int m, int op, int rho, int wg_threads)
+{
+    return simplex_set_shape(m, op, rho, wg_threads, 0);
 }
 
 int simplex_batch_launch(const struct simplex_job *jobs, int32_t njobs, void *stream)

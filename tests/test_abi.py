@@ -98,7 +98,7 @@ def test_set_tile_validation():
     with pytest.raises(smap.SimplexMapError):
         smap.set_tile(2, "accum", 24)
     with pytest.raises(smap.SimplexMapError):
-        smap.set_tile(4, "hash", 8, 64)
+        smap.set_tile(4, "hash", 8, 512)
     with pytest.raises(smap.SimplexMapError):
         smap.set_tile(2, "ca2", 256, wg_threads=512)
     with pytest.raises(smap.SimplexMapError):
@@ -280,3 +280,40 @@ def test_copy_probe_argument_errors():
     assert raw(2, 10, FAKE, FAKE + 120) == E                # overlap (box = 121 B)
     assert raw(3, 10, FAKE + 1330, FAKE) == E               # overlap (box = 1331 B)
     assert raw(3, 1 << 20, FAKE, FAKE + (1 << 40)) == smap.ERANGE
+
+
+def test_set_shape_validation_and_grouped_counts():
+    """Tiles per workgroup: only compiled groupings are accepted; the plan
+    reports ceil(units / tiles_per_wg) workgroups (BB: per row of the tile
+    grid along x_1)."""
+    bad = [(4, "hash", 8, 256, 3), (4, "hash", 8, 64, 8), (2, "accum", 32, 256, 4),
+           (3, "ca3", 256, 256, 2), (2, "ca2", 1024, 64, 4)]
+    for m, op, rho, wg, grp in bad:
+        with pytest.raises(smap.SimplexMapError) as e:
+            smap.set_shape(m, op, rho, wg, grp)
+        assert e.value.status == smap.EUNSUPPORTED, (m, op, rho, wg, grp)
+    for args in ((4, "hash", 8, -1, 4), (4, "hash", 8, 256, -1)):
+        with pytest.raises(smap.SimplexMapError) as e:
+            smap.set_shape(*args)
+        assert e.value.status == smap.EINVAL
+    try:
+        smap.set_shape(3, "ca3", 256, 256, 1)        # automata: 0 or 1
+        smap.set_shape(4, "hash", 8, 256, 0)          # first listed: two tiles per workgroup
+        assert smap.plan_info(4, 128, "hash")["tiles_per_wg"] == 2
+        smap.set_shape(4, "hash", 8, 256, 1)
+        assert smap.plan_info(4, 128, "hash")["tiles_per_wg"] == 1
+        for grp in (2, 4, 8):
+            smap.set_shape(4, "hash", 8, 256, grp)
+            h = smap.plan_info(4, 128, "hash")
+            assert h["tiles_per_wg"] == grp and h["wgs_per_tile"] == 1
+            assert h["launched_wgs"] == -(-h["launched_tiles"] // grp)
+            bb = smap.plan_info(4, 128, "hash", use_bb=True)
+            kb = -(-129 // 8)   # box tiles per axis
+            assert bb["launched_tiles"] == kb ** 4
+            assert bb["launched_wgs"] == -(-kb // grp) * kb ** 3
+        smap.set_shape(4, "hash", 4, 256, 16)
+        assert smap.plan_info(4, 128, "hash")["rho"] == 4
+    finally:
+        smap.set_tile(4, "hash", 0)
+        smap.set_tile(3, "ca3", 0)
+    assert smap.plan_info(4, 128, "hash")["tiles_per_wg"] == 2   # the default m = 4 shape

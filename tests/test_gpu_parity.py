@@ -20,6 +20,13 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 POINT_TILES = {2: [16, 32, 64, 128], 3: [8, 16, 32], 4: [4, 8, 16]}
+# (rho, threads, tiles per workgroup): one tile per workgroup at each compiled
+# rho, plus every compiled grouping of x_1-adjacent tiles
+POINT_SHAPES = {m: [(rho, 0, 1) for rho in POINT_TILES[m]] for m in POINT_TILES}
+POINT_SHAPES[2] += [(32, 64, 1), (32, 64, 2)]
+POINT_SHAPES[3] += [(16, 256, 2), (8, 256, 4), (16, 64, 1), (16, 64, 2)]
+POINT_SHAPES[4] += [(8, 256, 4), (8, 128, 4), (8, 256, 2), (8, 256, 8), (4, 256, 8), (4, 256, 16),
+                    (8, 64, 1), (8, 64, 2), (8, 64, 4), (8, 128, 2)]
 CA2_TILES = [(1024, 64), (1024, 128), (1024, 256), (512, 512), (256, 256), (128, 128),
              (2048, 128), (2048, 256), (4096, 256)]
 
@@ -90,13 +97,13 @@ def test_hits_cover_simplex_exactly_once(smap, m):
     try:
         for n in _sweep(m):
             want = to_dev(expected(m, n, "hits", None))
-            for rho in POINT_TILES[m]:
-                smap.set_tile(m, "hits", rho)
+            for rho, wg, grp in POINT_SHAPES[m]:
+                smap.set_shape(m, "hits", rho, wg, grp)
                 for kind, beta in kinds(m):
-                    say(f"hits m={m} n={n} rho={rho} {kind} beta={beta}")
+                    say(f"hits m={m} n={n} shape={rho},{wg},{grp} {kind} beta={beta}")
                     d = fresh_out(m, n, "hits")
                     launch(smap, kind, m, n, "hits", None, d, beta)
-                    assert same(d, want), (m, n, rho, kind, beta)
+                    assert same(d, want), (m, n, rho, wg, grp, kind, beta)
     finally:
         smap.set_tile(m, "hits", 0)
 
@@ -109,13 +116,13 @@ def test_pointwise_parity(smap, m, op):
             inp = si.box(m, n, "u31", 1000 + n) if op == "accum" else None
             want = to_dev(expected(m, n, op, inp))
             d_in = to_dev(inp) if inp is not None else None
-            for rho in POINT_TILES[m]:
-                smap.set_tile(m, op, rho)
+            for rho, wg, grp in POINT_SHAPES[m]:
+                smap.set_shape(m, op, rho, wg, grp)
                 for kind, beta in kinds(m):
-                    say(f"{op} m={m} n={n} rho={rho} {kind} beta={beta}")
+                    say(f"{op} m={m} n={n} shape={rho},{wg},{grp} {kind} beta={beta}")
                     d_out = fresh_out(m, n, op)
                     launch(smap, kind, m, n, op, d_in, d_out, beta)
-                    assert same(d_out, want), (m, n, rho, kind, beta)
+                    assert same(d_out, want), (m, n, rho, wg, grp, kind, beta)
     finally:
         smap.set_tile(m, op, 0)
 

@@ -62,11 +62,12 @@ def test_autotune_result_and_cache(smap, tmp_path, m, n, op):
     smap.map_launch(m, n, op, d_in, d_out2)
     torch.cuda.synchronize()
     assert np.array_equal(d_out2.cpu().numpy().view(want.dtype), want)
-    assert os.path.exists(cache) and "smap-tune-v1" in open(cache).read()
+    assert os.path.exists(cache) and "smap-tune-v2" in open(cache).read()
     # the cache returns the stored choice without timing
     smap.autotune_reset()
     again = smap.autotune(m, n, op, d_in, d_out, reps=5, cache_path=cache)
-    assert (again["rho"], again["wg_threads"], again["beta"]) == (best["rho"], best["wg_threads"], best["beta"])
+    keys = ("rho", "wg_threads", "tiles_per_wg", "beta")
+    assert tuple(again[k] for k in keys) == tuple(best[k] for k in keys)
     assert abs(again["us"] - best["us"]) < 1e-2
 
 
