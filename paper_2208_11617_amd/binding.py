@@ -194,22 +194,42 @@ def _need_bytes(op, m, n, which):
     return 4 * box
 
 
+_torch_mod = None
+
+
+def _torch():
+    """torch, imported on first use (the host-only calls do not need it)."""
+    global _torch_mod
+    if _torch_mod is None:
+        import torch
+        _torch_mod = torch
+    return _torch_mod
+
+
+def _dtype_name(t):
+    return str(t.dtype)[6:]            # "torch.uint8" -> "uint8"
+
+
 def _check_tensor(t, what, dtypes, nbytes, role, device=True):
     """Raise SimplexMapError(EINVAL) unless t is a contiguous device tensor of
     one of `dtypes` holding at least `nbytes` bytes.  Runs before any call
     into the library, so a wrong buffer never reaches a kernel."""
-    import torch
-    if not isinstance(t, torch.Tensor):
+    _check_layout(t, what, dtypes, nbytes, role)
+    if device and not t.is_cuda:
+        raise SimplexMapError(EINVAL, what, f"{role} must be a device (cuda) tensor")
+
+
+def _check_layout(t, what, dtypes, nbytes, role):
+    """The type, contiguity and size checks of _check_tensor."""
+    if not isinstance(t, _torch().Tensor):
         raise SimplexMapError(EINVAL, what, f"{role} must be a torch tensor, got {type(t).__name__}")
-    if str(t.dtype).replace("torch.", "") not in dtypes:
+    if _dtype_name(t) not in dtypes:
         raise SimplexMapError(EINVAL, what, f"{role} has dtype {t.dtype}; expected one of {dtypes}")
     if not t.is_contiguous():
         raise SimplexMapError(EINVAL, what, f"{role} must be contiguous")
     have = t.numel() * t.element_size()
     if have < nbytes:
         raise SimplexMapError(EINVAL, what, f"{role} holds {have} bytes; the launch needs {nbytes}")
-    if device and not t.is_cuda:
-        raise SimplexMapError(EINVAL, what, f"{role} must be a device (cuda) tensor")
 
 
 def _check_op_buffers(what, m, n, op, buf_in, buf_out):
@@ -221,9 +241,11 @@ def _check_op_buffers(what, m, n, op, buf_in, buf_out):
     din, dout = _OP_DTYPES[op]
     bufs = [(t, dt, which, role) for t, dt, which, role in
             ((buf_in, din, 0, "buf_in"), (buf_out, dout, 1, "buf_out")) if t is not None and dt is not None]
-    for device in (False, True):       # every buffer's type and size first, then the devices
-        for t, dt, which, role in bufs:
-            _check_tensor(t, what, dt, _need_bytes(op, m, n, which), role, device)
+    for t, dt, which, role in bufs:     # every buffer's type and size first, then the devices
+        _check_layout(t, what, dt, _need_bytes(op, m, n, which), role)
+    for t, dt, which, role in bufs:
+        if not t.is_cuda:
+            raise SimplexMapError(EINVAL, what, f"{role} must be a device (cuda) tensor")
 
 
 def _stream(stream):
