@@ -391,7 +391,8 @@ int dispatch_point(int op, int m, const TileCfg &tc, const Plan &P, dim3 grid, c
     case OP_HITS: return dispatch_point_shape<OP_HITS, BB>(m, tc, P, grid, in, out, s);
     case OP_HASH: return dispatch_point_shape<OP_HASH, BB>(m, tc, P, grid, in, out, s);
     case OP_EDM:
-        if (m != 2 || tc.grp != 1) return kEinval;
+        if (m != 2) return kEinval;
+        if (tc.grp != 1) return kEunsupported;       // one tile per workgroup only
         switch (tc.rho) {
         case 32: launch_point<2, 32, 256, 1, OP_EDM, BB>(P, grid, in, out, s); return kOk;
         case 16: launch_point<2, 16, 64, 1, OP_EDM, BB>(P, grid, in, out, s); return kOk;
@@ -1184,7 +1185,7 @@ int autotune(int m, int64_t n, int op, const void *in, void *out, int32_t reps, 
             }
             int lr = kOk;
             for (int i = 0; i < 2 && lr == kOk; ++i) lr = do_launch(m, n, 0, beta, op, in, out, stream, false);
-            if (lr == kErange) continue;  // this tile does not fit the index range
+            if (lr == kErange || lr == kEunsupported) continue;  // not for this size or op
             if (lr != kOk) { rc = lr; break; }
             if (hipEventRecord(e0, s) != hipSuccess) { rc = kEhip; break; }
             for (int i = 0; i < reps && lr == kOk; ++i) lr = do_launch(m, n, 0, beta, op, in, out, stream, false);

@@ -218,8 +218,8 @@ __device__ __forceinline__ T pick_u(const T (&v)[U], int u)
 // (the cube cells of a level run along x_1; a folded run is reversed), so
 // the lanes of a wave stand side by side across the U tiles: a strip row
 // is U tile rows of 4 rho bytes each, G lanes per tile, and a wave's store
-// covers U times the contiguous bytes of one tile row -- whole cache lines
-// instead of a quarter line at rho = 8, m = 4.  The U decodes are
+// covers U times the contiguous bytes of one tile row (64 bytes instead of
+// 32 at rho = 8, U = 2, m = 4).  The U decodes are
 // workgroup-uniform scalar code, and each lane selects its own tile's
 // origin once; units past the end of the grid, discarded units and tiles
 // outside the simplex leave their lanes idle.  The strip rows a lane visits

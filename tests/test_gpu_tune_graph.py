@@ -145,3 +145,24 @@ def test_queue_graph_replays(smap):
                     assert torch.equal(outs[k], refs[k]), (cap, rep, m, n)
         finally:
             g.close()
+
+
+def test_autotune_edm_skips_grouped_shapes(smap):
+    """EDM runs one tile per workgroup only: the tuner passes over the
+    grouped pointwise shapes and returns an ungrouped one, bit-for-bit the
+    same distances as the default launch."""
+    n = 500
+    pts = torch.from_numpy(si.points(n, 7300)).cuda()
+    ref = dev(si.sentinel_box(2, n, np.uint32))
+    smap.map_launch(2, n, "edm", pts, ref)
+    out = dev(si.sentinel_box(2, n, np.uint32))
+    try:
+        best = smap.autotune(2, n, "edm", pts, out, reps=3)
+        torch.cuda.synchronize()
+        assert best["tiles_per_wg"] == 1 and best["us"] > 0
+        again = dev(si.sentinel_box(2, n, np.uint32))
+        smap.map_launch(2, n, "edm", pts, again)
+        torch.cuda.synchronize()
+        assert torch.equal(again, ref)
+    finally:
+        smap.autotune_reset()
