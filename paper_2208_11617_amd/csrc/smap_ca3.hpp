@@ -266,41 +266,24 @@ __device__ __forceinline__ void ca3_tile(const Plan &P, const uint8_t *__restric
     }
 }
 
-// The CA3 kernel.  BB: grid (kbox, kbox, kbox * SUB).  H, ORD = 0: grid
-// (map grid, SUB); x-adjacent tiles of one sub-block position run together.
-// H, ORD = 1: a 1-D grid in which the SUBY sub-blocks that share a tile and
-// a z range (the y-neighbours, whose halo rows overlap) run one after
-// another on one XCD: hardware workgroup L goes to XCD L mod 8, its slot
-// L / 8 on that XCD is (chunk sequence, y sub-block), and the chunks
-// (tile, z range) are dealt to the XCDs in turn, z range slowest.  The grid
-// is padded to whole rounds of 8 chunks; P.grid_div[0] divides by the
-// map's tile count.
-template <int RHO, int RY, int RZ, int RL, bool BB, bool SAFE, int PD = 2, int ORD = 0>
+// The CA3 kernel.  BB: grid (kbox, kbox, kbox * SUB).  H: grid (map grid,
+// SUB); x-adjacent tiles of one sub-block position run together.
+template <int RHO, int RY, int RZ, int RL, bool BB, bool SAFE>
 __global__ __launch_bounds__((RHO / 16) * (RY / RL)) void k_ca3(const Plan P, const uint8_t *__restrict__ in,
                                                                        uint8_t *__restrict__ out)
 {
-    using Sh = Ca3Walk<RHO, RY, RZ, RL>;
-    constexpr int SUB = Sh::SUB, SUBY = Sh::SUBY;
+    constexpr int SUB = Ca3Walk<RHO, RY, RZ, RL>::SUB;
     int32_t t[4] = {0, 0, 0, 0};
     uint32_t sub;
+    const WgId g = wg_id(P);
     if (BB) {
-        const WgId g = wg_id(P);
         decode_bb(P, g.x, g.y, g.z / SUB, t);
         sub = g.z % SUB;
-    } else if (ORD == 1) {
-        const uint32_t L = blockIdx.x;
-        const uint32_t slot = L >> 3;
-        const uint32_t chunk = (slot / SUBY) * 8u + (L & 7u);
-        const uint32_t zb = divu(chunk, P.grid_div[0]);
-        if (zb >= (uint32_t)Sh::SUBZ) return;        // padding of the last round
-        if (!decode_h<3>(P, chunk - zb * P.total, t)) return;
-        sub = zb * SUBY + slot % SUBY;
     } else {
-        const WgId g = wg_id(P);
         if (!decode_h<3>(P, g.x, t)) return;
         sub = g.y;
     }
-    ca3_tile<RHO, RY, RZ, RL, SAFE, PD>(P, in, out, t, sub);
+    ca3_tile<RHO, RY, RZ, RL, SAFE>(P, in, out, t, sub);
 }
 
 }  // namespace smap

@@ -404,34 +404,14 @@ int dispatch_point(int op, int m, const TileCfg &tc, const Plan &P, dim3 grid, c
     return kEinval;
 }
 
-// CA3 launch order (H): 0 = grid (map units, sub-blocks), hardware order;
-// 1 = the y-neighbour sub-blocks of a tile and z range one after another on
-// one XCD (k_ca3's ORD = 1 grid).  Prefetch depth: planes of chunk loads in
-// flight per workgroup.
-#ifndef SMAP_CA3_ORD
-#define SMAP_CA3_ORD 0
-#endif
-#ifndef SMAP_CA3_PD
-#define SMAP_CA3_PD 2
-#endif
 template <int RHO, int RY, int RZ, int RL, bool BB>
-void launch_ca3(Plan PL, dim3 grid, const uint8_t *in, uint8_t *out, hipStream_t s)
+void launch_ca3(const Plan &PL, dim3 grid, const uint8_t *in, uint8_t *out, hipStream_t s)
 {
-    constexpr int ORD = BB ? 0 : SMAP_CA3_ORD;
-    if (ORD == 1) {
-        using Sh = Ca3Walk<RHO, RY, RZ, RL>;
-        const uint64_t chunks = (uint64_t)PL.total * Sh::SUBZ;   // (tile, z range) pairs
-        grid = dim3((uint32_t)((chunks + 7) / 8 * 8 * Sh::SUBY), 1, 1);
-        PL.grid[0] = grid.x;
-        PL.grid[1] = PL.grid[2] = 1;
-        PL.nwg = grid.x;
-        PL.grid_div[0] = make_divu(PL.total);
-        PL.remap = 0;
-    }
+    constexpr int NT = Ca3Walk<RHO, RY, RZ, RL>::NT;
     if (PL.n < 15)
-        hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, true, SMAP_CA3_PD, ORD>), grid, dim3(Ca3Walk<RHO, RY, RZ, RL>::NT), 0, s, PL, in, out);
+        hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, true>), grid, dim3(NT), 0, s, PL, in, out);
     else
-        hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, false, SMAP_CA3_PD, ORD>), grid, dim3(Ca3Walk<RHO, RY, RZ, RL>::NT), 0, s, PL, in, out);
+        hipLaunchKernelGGL((k_ca3<RHO, RY, RZ, RL, BB, false>), grid, dim3(NT), 0, s, PL, in, out);
 }
 
 template <bool BB>
@@ -467,10 +447,7 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
     // faster in the hardware order: MAP (no memory traffic to share) and the
     // 3-D automaton (its sub-major order already spreads the concurrent
     // workgroups over the buffer).
-#ifndef SMAP_CA3_REMAP
-#define SMAP_CA3_REMAP 0
-#endif
-    PL.remap = (BB || (op == OP_CA3 && !SMAP_CA3_REMAP) || op == OP_MAP) ? 0u : 1u;
+    PL.remap = (BB || op == OP_CA3 || op == OP_MAP) ? 0u : 1u;
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
         uint8_t *o8 = (uint8_t *)out;
