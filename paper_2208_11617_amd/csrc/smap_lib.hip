@@ -42,7 +42,7 @@ struct Ca2Shape {
     int rho, wg, w, r, sub;
 };
 constexpr Ca2Shape kCa2Shapes[] = {
-    {1024, 64, 1, 16, 64}, {1024, 128, 2, 16, 32}, {1024, 256, 4, 16, 16},
+    {1024, 64, 1, 4, 256}, {1024, 128, 2, 16, 32}, {1024, 256, 4, 16, 16},
     {512, 512, 8, 16, 2},  {256, 256, 4, 16, 1},   {128, 128, 2, 8, 1},
     // waves side by side along x: 1 KB columns, 2 or 4 per workgroup
     {2048, 128, 2, 16, 128}, {2048, 256, 4, 16, 64}, {4096, 256, 4, 16, 256},
@@ -95,7 +95,7 @@ constexpr int64_t kCa3LargeTileN = 768;
 
 TileCfg default_tile(int m, int64_t n, int cls)
 {
-    if (cls == 1) return {1024, 64, 64};
+    if (cls == 1) return {1024, 64, 256};
     if (cls == 2) {
         if (n >= kCa3LargeTileN) return {256, 256, (256 / 32) * (256 / ca3_rz(256))};
         return {128, 256, (128 / 64) * (128 / ca3_rz(128))};
@@ -441,13 +441,13 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
     PL.grid_div[1] = make_divu(grid.y);
     // H runs XCD-contiguous (its workgroups are nearly all useful, so every
     // XCD gets an equal share of the work) when neighbouring tiles share
-    // cache lines: the pointwise ops that touch memory and the 2-D
-    // automaton.  BB keeps the hardware order: a contiguous split would hand
-    // the XCDs at the end of the range mostly empty box tiles.  Measured
-    // faster in the hardware order: MAP (no memory traffic to share) and the
-    // 3-D automaton (its sub-major order already spreads the concurrent
-    // workgroups over the buffer).
-    PL.remap = (BB || op == OP_CA3 || op == OP_MAP) ? 0u : 1u;
+    // cache lines: the pointwise ops that touch memory.  BB keeps the
+    // hardware order: a contiguous split would hand the XCDs at the end of
+    // the range mostly empty box tiles.  Measured faster in the hardware
+    // order: MAP (no memory traffic to share) and the automata (their
+    // sub-block order already spreads the concurrent workgroups over the
+    // buffer; 2-D: 66.8 against 69.6 us at n = 16384).
+    PL.remap = (BB || op == OP_CA2 || op == OP_CA3 || op == OP_MAP) ? 0u : 1u;
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
         uint8_t *o8 = (uint8_t *)out;
@@ -464,7 +464,7 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
             else                                                                                  \
                 hipLaunchKernelGGL((k_ca2<RHO, W, R, D, BB, false, WX>), grid, dim3(WG), 0, s, PL, i8, o8); \
             return kOk;
-        SMAP_CA2(1024, 64, 1, 16, 1)
+        SMAP_CA2(1024, 64, 1, 4, 1)
         SMAP_CA2(1024, 128, 2, 16, 1)
         SMAP_CA2(1024, 256, 4, 16, 1)
         SMAP_CA2(512, 512, 8, 16, 1)

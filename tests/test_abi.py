@@ -118,7 +118,7 @@ def test_set_tile_validation():
     assert info["launched_wgs"] == 16 * info["launched_tiles"]
     smap.set_tile(2, "ca2", 0)
     info = smap.plan_info(2, 16384, "ca2")
-    assert info["rho"] == 1024 and info["wg_threads"] == 64 and info["wgs_per_tile"] == 64
+    assert info["rho"] == 1024 and info["wg_threads"] == 64 and info["wgs_per_tile"] == 256
 
 
 def test_plan_info_fields():
