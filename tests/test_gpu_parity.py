@@ -193,6 +193,101 @@ def test_ca3_parity(smap):
         smap.set_tile(3, "ca3", 0)
 
 
+def test_ca3_unaligned_buffers(smap):
+    """Boxes that start k bytes past a 16-byte boundary, for input and
+    output: the CA3 staging loads and the stores then meet every alignment
+    of a row against 16 bytes, including the first row of the buffer; the
+    bytes around the output view stay untouched."""
+    cases = [(15, (1, 5, 8, 15)), (16, (3, 12)), (17, (0, 7, 14)), (40, (1, 9)), (130, (4, 11)),
+             (300, (2, 13))]
+    try:
+        for n, shifts in cases:
+            inp = si.box(3, n, "bern", 3300 + n, p=0.3)
+            want = to_dev(expected(3, n, "ca3", inp)).reshape(-1)
+            src = to_dev(inp).reshape(-1)
+            total = (n + 1) ** 3
+            for k in shifts:
+                raw_in = torch.zeros(total + 32, dtype=torch.uint8, device="cuda")
+                d_in = raw_in[k:k + total]
+                d_in.copy_(src)
+                ko = (7 * k + 3) % 16
+                for rho, wg in ((256, 256), (128, 256), (64, 128), (32, 64)):
+                    smap.set_tile(3, "ca3", rho, wg)
+                    for kind in ("h", "bb"):
+                        say(f"ca3 unaligned n={n} in+{k} out+{ko} rho={rho} wg={wg} {kind}")
+                        raw_out = torch.full((total + 32,), si.SENTINEL_U8, dtype=torch.uint8, device="cuda")
+                        d_out = raw_out[ko:ko + total]
+                        launch(smap, kind, 3, n, "ca3", d_in, d_out)
+                        assert same(d_out, want), (n, k, ko, rho, wg, kind)
+                        assert bool((raw_out[:ko] == si.SENTINEL_U8).all()), (n, k, ko, rho, kind)
+                        assert bool((raw_out[ko + total:] == si.SENTINEL_U8).all()), (n, k, ko, rho, kind)
+    finally:
+        smap.set_tile(3, "ca3", 0)
+
+
+def test_ca2_unaligned_buffers(smap):
+    """The 2-D step on boxes that start k bytes past a 16-byte boundary (input
+    and output), at several tiles; the bytes around the output view stay
+    untouched."""
+    try:
+        for n in (15, 16, 17, 100, 1000, 2100):
+            inp = si.box(2, n, "bern", 2300 + n, p=0.3)
+            want = to_dev(expected(2, n, "ca2", inp)).reshape(-1)
+            src = to_dev(inp).reshape(-1)
+            total = (n + 1) ** 2
+            for k in (1, 7, 13):
+                raw_in = torch.zeros(total + 32, dtype=torch.uint8, device="cuda")
+                d_in = raw_in[k:k + total]
+                d_in.copy_(src)
+                ko = (5 * k + 2) % 16
+                for rho, wg in ((1024, 64), (256, 256), (128, 128)):
+                    smap.set_tile(2, "ca2", rho, wg)
+                    for kind in ("h", "bb"):
+                        say(f"ca2 unaligned n={n} in+{k} out+{ko} rho={rho} wg={wg} {kind}")
+                        raw_out = torch.full((total + 32,), si.SENTINEL_U8, dtype=torch.uint8, device="cuda")
+                        d_out = raw_out[ko:ko + total]
+                        launch(smap, kind, 2, n, "ca2", d_in, d_out)
+                        assert same(d_out, want), (n, k, ko, rho, wg, kind)
+                        assert bool((raw_out[:ko] == si.SENTINEL_U8).all()), (n, k, ko, rho, kind)
+                        assert bool((raw_out[ko + total:] == si.SENTINEL_U8).all()), (n, k, ko, rho, kind)
+    finally:
+        smap.set_tile(2, "ca2", 0)
+
+
+@pytest.mark.parametrize("op", ["accum", "hash", "hits"])
+def test_pointwise_unaligned_buffers(smap, op):
+    """The 32-bit element ops on boxes that start 4, 8 or 12 bytes past a
+    16-byte boundary (input and output), one tile per workgroup and grouped;
+    the words around the output view stay untouched."""
+    sent = si.SENTINEL_U32 - (1 << 32)
+    cases = {2: (40, 257), 3: (33, 70), 4: (17, 40)}
+    for m, ns in cases.items():
+        shapes = [(0, 0, 1)] + [s for s in POINT_SHAPES[m] if s[2] > 1][:1]
+        try:
+            for n in ns:
+                inp = si.box(m, n, "u31", 1700 + n) if op == "accum" else None
+                want = to_dev(expected(m, n, op, inp)).reshape(-1)
+                total = (n + 1) ** m
+                for k in (1, 2, 3):
+                    d_in = None
+                    if inp is not None:
+                        raw_in = torch.zeros(total + 8, dtype=torch.int32, device="cuda")
+                        d_in = raw_in[k:k + total]
+                        d_in.copy_(to_dev(inp).reshape(-1))
+                    ko = 4 - k
+                    for rho, wg, grp in shapes:
+                        smap.set_shape(m, op, rho, wg, grp)
+                        for kind, beta in kinds(m):
+                            say(f"{op} unaligned m={m} n={n} in+{4 * k} out+{4 * ko} shape={rho},{wg},{grp} {kind}")
+                            raw_out = torch.full((total + 8,), sent, dtype=torch.int32, device="cuda")
+                            d_out = raw_out[ko:ko + total]
+                            launch(smap, kind, m, n, op, d_in, d_out, beta)
+                            assert same(d_out, want), (m, n, k, rho, wg, grp, kind, beta)
+                            assert bool((raw_out[:ko] == sent).all()) and bool((raw_out[ko + total:] == sent).all())
+        finally:
+            smap.set_tile(m, op, 0)
+
+
 def test_ca2_two_steps_ping_pong(smap):
     n = 700
     a = si.box(2, n, "bern", 77, p=0.35)
