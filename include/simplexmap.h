@@ -170,9 +170,9 @@ int simplex_plan_tiles(int m, int64_t n, int r, int beta, int op, int use_bb,
  *              on a 1024-byte column of the tile.
  *   Large tiles are split into sub-blocks of rows (and planes), one
  *   workgroup each (wgs_per_tile in the plan info).
- *   CA3 (m=3): rho 256 (256 threads; the default from n = 768 on), 128
- *              (256, the default below n = 768; or 128 or 512), 64 (128 or
- *              256), 32 (64).
+ *   CA3 (m=3): rho 256 (256 threads, the default from n = 768 on; or 128
+ *              or 512), 128 (256, the default below n = 768; or 128 or
+ *              512), 64 (128 or 256), 32 (64).
  * wg_threads = 0 picks the first listed size; any other value must be one
  * of the listed sizes.
  */

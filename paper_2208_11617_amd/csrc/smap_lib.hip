@@ -80,7 +80,9 @@ constexpr Ca3Shape kCa3Shapes[] = {
     {128, 256, 64, ca3_rz(128), 2, (128 / 64) * (128 / ca3_rz(128))},
     {128, 128, 32, ca3_rz(128), 2, (128 / 32) * (128 / ca3_rz(128))},
     {128, 512, 128, ca3_rz(128), 2, (128 / 128) * (128 / ca3_rz(128))},
-    {256, 256, 32, ca3_rz(256), 2, (256 / 32) * (256 / ca3_rz(256))},
+    {256, 256, 16, ca3_rz(256), 1, (256 / 16) * (256 / ca3_rz(256))},
+    {256, 128, 8, ca3_rz(256), 1, (256 / 8) * (256 / ca3_rz(256))},
+    {256, 512, 32, ca3_rz(256), 1, (256 / 32) * (256 / ca3_rz(256))},
     {64, 128, 64, ca3_rz(64), 2, (64 / 64) * (64 / ca3_rz(64))},
     {64, 256, 64, ca3_rz(64), 1, (64 / 64) * (64 / ca3_rz(64))},
     {32, 64, 32, ca3_rz(32), 1, (32 / 32) * (32 / ca3_rz(32))},
@@ -97,7 +99,7 @@ TileCfg default_tile(int m, int64_t n, int cls)
 {
     if (cls == 1) return {1024, 64, 256};
     if (cls == 2) {
-        if (n >= kCa3LargeTileN) return {256, 256, (256 / 32) * (256 / ca3_rz(256))};
+        if (n >= kCa3LargeTileN) return {256, 256, (256 / 16) * (256 / ca3_rz(256))};
         return {128, 256, (128 / 64) * (128 / ca3_rz(128))};
     }
     for (const PointShape &c : kPointShapes)  // the first listed shape of an m is its default
@@ -489,7 +491,9 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
         SMAP_CA3(128, 256, 64, ca3_rz(128), 2)
         SMAP_CA3(128, 128, 32, ca3_rz(128), 2)
         SMAP_CA3(128, 512, 128, ca3_rz(128), 2)
-        SMAP_CA3(256, 256, 32, ca3_rz(256), 2)
+        SMAP_CA3(256, 256, 16, ca3_rz(256), 1)
+        SMAP_CA3(256, 128, 8, ca3_rz(256), 1)
+        SMAP_CA3(256, 512, 32, ca3_rz(256), 1)
         SMAP_CA3(64, 128, 64, ca3_rz(64), 2)
         SMAP_CA3(64, 256, 64, ca3_rz(64), 1)
         SMAP_CA3(32, 64, 32, ca3_rz(32), 1)

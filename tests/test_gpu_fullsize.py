@@ -82,21 +82,23 @@ def test_workload_whole_box(smap, name):
 
 @pytest.mark.parametrize("layout", ["packed", "levels"])
 def test_ca3_rho256_across_tile_faces(smap, layout):
-    """The 256^3 CA3 tile with neighbouring tiles on every face: whole boxes
-    at n = 511, 512, 513 (two tiles per side, the last one ragged) and 767."""
+    """The 256^3 CA3 tile (256- and 128-thread sub-block shapes) with
+    neighbouring tiles on every face: whole boxes at n = 511, 512, 513 (two
+    tiles per side, the last one ragged) and 767."""
     smap.set_layout(3, {"packed": smap.LAYOUT_PACKED, "levels": smap.LAYOUT_LEVELS}[layout])
-    smap.set_tile(3, "ca3", 256, 256)
     try:
         for n in (511, 512, 513, 767):
-            say(f"ca3 rho 256 layout={layout} n={n}")
             inp = fullsize.box(3, n, "bern", 3700 + n, 0.2 if n % 2 else 0.3)
             want = dev(fullsize.expected(3, n, "ca3", inp))
             d_in = dev(inp)
-            for kind in ("h", "bb"):
-                d_out = fresh(3, n, True)
-                run(smap, kind, 3, n, "ca3", d_in, d_out)
-                if not torch.equal(d_out, want):
-                    pytest.fail(f"n={n} {kind}: first difference {first_difference(d_out, want)}")
+            for wg in (256, 128):
+                smap.set_tile(3, "ca3", 256, wg)
+                say(f"ca3 rho 256 threads {wg} layout={layout} n={n}")
+                for kind in ("h", "bb"):
+                    d_out = fresh(3, n, True)
+                    run(smap, kind, 3, n, "ca3", d_in, d_out)
+                    if not torch.equal(d_out, want):
+                        pytest.fail(f"n={n} threads={wg} {kind}: first difference {first_difference(d_out, want)}")
     finally:
         smap.set_tile(3, "ca3", 0)
         smap.set_layout(3, smap.LAYOUT_AUTO)

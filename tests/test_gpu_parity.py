@@ -173,7 +173,8 @@ def test_ca2_parity(smap):
 CA3_SIZES = list(range(0, 41)) + [62, 63, 64, 65, 66, 95, 96, 97, 127, 128, 150]
 
 
-CA3_TILES = [(128, 256), (128, 128), (128, 512), (256, 256), (64, 128), (64, 256), (32, 64)]
+CA3_TILES = [(128, 256), (128, 128), (128, 512), (256, 256), (256, 128), (256, 512), (64, 128), (64, 256),
+             (32, 64)]
 
 
 def test_ca3_parity(smap):
@@ -211,7 +212,7 @@ def test_ca3_unaligned_buffers(smap):
                 d_in = raw_in[k:k + total]
                 d_in.copy_(src)
                 ko = (7 * k + 3) % 16
-                for rho, wg in ((256, 256), (128, 256), (64, 128), (32, 64)):
+                for rho, wg in ((256, 256), (256, 128), (128, 256), (64, 128), (32, 64)):
                     smap.set_tile(3, "ca3", rho, wg)
                     for kind in ("h", "bb"):
                         say(f"ca3 unaligned n={n} in+{k} out+{ko} rho={rho} wg={wg} {kind}")
