@@ -77,9 +77,9 @@ struct Ca3Shape {
 };
 constexpr int ca3_rz(int rho) { return SMAP_CA3_RZ < rho ? SMAP_CA3_RZ : rho; }
 constexpr Ca3Shape kCa3Shapes[] = {
-    {128, 256, 64, ca3_rz(128), 2, (128 / 64) * (128 / ca3_rz(128))},
-    {128, 128, 32, ca3_rz(128), 2, (128 / 32) * (128 / ca3_rz(128))},
-    {128, 512, 128, ca3_rz(128), 2, (128 / 128) * (128 / ca3_rz(128))},
+    {128, 256, 32, ca3_rz(128), 1, (128 / 32) * (128 / ca3_rz(128))},
+    {128, 128, 16, ca3_rz(128), 1, (128 / 16) * (128 / ca3_rz(128))},
+    {128, 512, 64, ca3_rz(128), 1, (128 / 64) * (128 / ca3_rz(128))},
     {256, 256, 16, ca3_rz(256), 1, (256 / 16) * (256 / ca3_rz(256))},
     {256, 128, 8, ca3_rz(256), 1, (256 / 8) * (256 / ca3_rz(256))},
     {256, 512, 32, ca3_rz(256), 1, (256 / 32) * (256 / ca3_rz(256))},
@@ -98,9 +98,10 @@ constexpr int64_t kCa3LargeTileN = 768;
 TileCfg default_tile(int m, int64_t n, int cls)
 {
     if (cls == 1) return {1024, 64, 256};
-    if (cls == 2) {
-        if (n >= kCa3LargeTileN) return {256, 256, (256 / 16) * (256 / ca3_rz(256))};
-        return {128, 256, (128 / 64) * (128 / ca3_rz(128))};
+    if (cls == 2) {  // the first listed shape of the tile side (256 threads)
+        const int rho = n >= kCa3LargeTileN ? 256 : 128;
+        for (const Ca3Shape &c : kCa3Shapes)
+            if (c.rho == rho) return {c.rho, c.wg, c.sub};
     }
     for (const PointShape &c : kPointShapes)  // the first listed shape of an m is its default
         if (c.m == m) return {c.rho, c.wg, c.sub, c.grp};
@@ -488,9 +489,9 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
             static_assert(Ca3Walk<RHO, RY, RZ, RL>::NT == WG, "CA3 shape");                      \
             launch_ca3<RHO, RY, RZ, RL, BB>(PL, grid, i8, o8, s);                                 \
             return kOk;
-        SMAP_CA3(128, 256, 64, ca3_rz(128), 2)
-        SMAP_CA3(128, 128, 32, ca3_rz(128), 2)
-        SMAP_CA3(128, 512, 128, ca3_rz(128), 2)
+        SMAP_CA3(128, 256, 32, ca3_rz(128), 1)
+        SMAP_CA3(128, 128, 16, ca3_rz(128), 1)
+        SMAP_CA3(128, 512, 64, ca3_rz(128), 1)
         SMAP_CA3(256, 256, 16, ca3_rz(256), 1)
         SMAP_CA3(256, 128, 8, ca3_rz(256), 1)
         SMAP_CA3(256, 512, 32, ca3_rz(256), 1)
