@@ -115,7 +115,7 @@ struct Plan {
     uint32_t grid[3];            // launch grid of this launch (set per launch)
     Divu grid_div[2];            // division by grid[0], grid[1] (set per launch)
     uint32_t nwg;                // grid[0] * grid[1] * grid[2] (< 2^32)
-    uint32_t remap;              // 1: renumber workgroups with xcd_remap
+    uint32_t remap;              // workgroup order: 0 hardware, 1 xcd_remap, 2 xcd_scatter
     int32_t layout3;             // m = 3 native part: 0 packed grid, 1 one range per level
     uint32_t wg_base;            // first map index of this launch (0; a piece's start when
                                  // the pieces run as launches of their own)
@@ -135,6 +135,21 @@ SMAP_HD uint32_t xcd_remap(uint32_t L, uint32_t nwg)
     return x * per + (x < rem ? x : rem) + (L >> 3);
 }
 
+// BB launches: L -> xcd_scatter(L) rotates the ids inside each aligned group
+// of 8 by a pseudo-random amount (the top three bits of a multiplicative
+// hash of the group index), so the workgroups of one grid column meet every
+// XCD.  In the plain order an x extent that shares a factor with 8 ties each
+// column of box tiles to fixed XCDs, and the simplex's work sits in the low
+// columns: with 4 tiles per side the 3-D step ran 2.5x longer than with 3
+// or 5.  Ids stay inside their group, so the order is otherwise unchanged;
+// a last, partial group keeps its ids.  A bijection of [0, nwg).
+SMAP_HD uint32_t xcd_scatter(uint32_t L, uint32_t nwg)
+{
+    if ((L | 7u) >= nwg) return L;
+    const uint32_t h = ((L >> 3) * 0x9E3779B1u) >> 29;
+    return (L & ~7u) | ((L + h) & 7u);
+}
+
 #if defined(__HIPCC__)
 // Logical workgroup coordinates of this workgroup in the launch grid.
 struct WgId {
@@ -142,15 +157,14 @@ struct WgId {
 };
 __device__ __forceinline__ WgId wg_id(const Plan &P)
 {
-#ifndef SMAP_NO_XCD_REMAP
     if (P.remap) {
-        if (P.grid[1] == 1 && P.grid[2] == 1) return {xcd_remap(blockIdx.x, P.nwg), 0u, 0u};  // 1-D: no division
+        if (P.remap == 1 && P.grid[1] == 1 && P.grid[2] == 1)
+            return {xcd_remap(blockIdx.x, P.nwg), 0u, 0u};  // 1-D: no division
         const uint32_t L = (blockIdx.z * P.grid[1] + blockIdx.y) * P.grid[0] + blockIdx.x;
-        const uint32_t g = xcd_remap(L, P.nwg);
+        const uint32_t g = P.remap == 1 ? xcd_remap(L, P.nwg) : xcd_scatter(L, P.nwg);
         const uint32_t r = divu(g, P.grid_div[0]), r2 = divu(r, P.grid_div[1]);
         return {g - r * P.grid[0], r - r2 * P.grid[1], r2};
     }
-#endif
     return {blockIdx.x, blockIdx.y, blockIdx.z};
 }
 #endif

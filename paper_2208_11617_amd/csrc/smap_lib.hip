@@ -444,13 +444,18 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
     PL.grid_div[1] = make_divu(grid.y);
     // H runs XCD-contiguous (its workgroups are nearly all useful, so every
     // XCD gets an equal share of the work) when neighbouring tiles share
-    // cache lines: the pointwise ops that touch memory.  BB keeps the
-    // hardware order: a contiguous split would hand the XCDs at the end of
-    // the range mostly empty box tiles.  Measured faster in the hardware
-    // order: MAP (no memory traffic to share) and the automata (their
-    // sub-block order already spreads the concurrent workgroups over the
-    // buffer; 2-D: 66.8 against 69.6 us at n = 16384).
-    PL.remap = (BB || op == OP_CA2 || op == OP_CA3 || op == OP_MAP) ? 0u : 1u;
+    // cache lines: the pointwise ops that touch memory.  Measured faster in
+    // the hardware order: MAP (no memory traffic to share) and the automata
+    // (their sub-block order already spreads the concurrent workgroups over
+    // the buffer; 2-D: 66.8 against 69.6 us at n = 16384).  BB never splits
+    // contiguously (the XCDs at the end of the range would get mostly empty
+    // box tiles).  For the automata it scatters each group of 8 ids over
+    // the XCDs: the plain order ties the useful tile columns to a few XCDs
+    // when the box side shares a factor with 8 (3-D, n = 768-1023: 248-329
+    // against 106-172 us).  The pointwise ops keep the plain order (4-D
+    // hash: 29.9 against 34.7 us scattered).
+    PL.remap = BB ? ((op == OP_CA2 || op == OP_CA3) ? 2u : 0u)
+                  : ((op == OP_CA2 || op == OP_CA3 || op == OP_MAP) ? 0u : 1u);
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
         uint8_t *o8 = (uint8_t *)out;
@@ -1350,7 +1355,7 @@ int steps_launch(int m, int64_t n, int r, int beta, int op, int32_t steps, void 
     P.nwg = grid.x * grid.y * grid.z;
     P.grid_div[0] = make_divu(grid.x);
     P.grid_div[1] = make_divu(grid.y);
-    P.remap = bb ? 0u : 1u;
+    P.remap = bb ? 2u : 1u;
     // passes of at most kStepsKh generations, alternating a -> b -> a ...;
     // an odd number of passes, so that the last one writes b
     const int kh = ca3 ? kSteps3Kh : kStepsKh;   // generations per pass at most
