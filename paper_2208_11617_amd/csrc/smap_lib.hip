@@ -69,13 +69,12 @@ constexpr PointShape kPointShapes[] = {
 };
 
 // CA3 shapes: (rho, threads) -> rows RY (y), planes RZ (z), rows per lane RL.
-#ifndef SMAP_CA3_RZ
-#define SMAP_CA3_RZ 8
-#endif
+// Sub-blocks are 8 planes deep (4 and 16 measured slower at rho = 256).
 struct Ca3Shape {
     int rho, wg, ry, rz, rl, sub;
 };
-constexpr int ca3_rz(int rho) { return SMAP_CA3_RZ < rho ? SMAP_CA3_RZ : rho; }
+constexpr int kCa3Rz = 8;
+constexpr int ca3_rz(int rho) { return kCa3Rz < rho ? kCa3Rz : rho; }
 constexpr Ca3Shape kCa3Shapes[] = {
     {128, 256, 32, ca3_rz(128), 1, (128 / 32) * (128 / ca3_rz(128))},
     {128, 128, 16, ca3_rz(128), 1, (128 / 16) * (128 / ca3_rz(128))},
@@ -459,10 +458,7 @@ int dispatch(int m, int op, const TileCfg &tc, const Plan &P0, const void *in, v
     if (op == OP_CA2) {
         const uint8_t *i8 = (const uint8_t *)in;
         uint8_t *o8 = (uint8_t *)out;
-#ifndef SMAP_CA2_D
-#define SMAP_CA2_D 2
-#endif
-        constexpr int D = SMAP_CA2_D;  // rows per block; two blocks in flight per wave
+        constexpr int D = 2;  // rows per block; two blocks in flight per wave
         switch (tc.rho * 10000 + tc.wg) {
 #define SMAP_CA2(RHO, WG, W, R, WX)                                                              \
         case RHO * 10000 + WG:                                                                    \
